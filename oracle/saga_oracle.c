@@ -1,0 +1,224 @@
+/* Sequential Sparse SAGA oracle -- plain C, FP64, one thread.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load or call this code.  It shares no
+ * code, header or table with the HIP library it checks.
+ *
+ * What it computes (paper: Leblond, Pedregosa & Lacoste-Julien, "ASAGA:
+ * Asynchronous Parallel SAGA", AISTATS 2017):
+ *
+ *   problem   min_x f(x) = (1/n) sum_i f_i(x)                (Section 1, Eq. finiteSum)
+ *             f_i(x) = phi(a_i . x; b_i) + (lambda/2) ||x||^2
+ *             logistic phi(z; b) = log(1 + exp(-b z))         (Section 4.1, "Models")
+ *             squared  phi(z; b) = (z - b)^2 / 2              (least squares; not in the
+ *                                                              paper, reading of the ridge
+ *                                                              closed form (A'A/n+lI)^-1 A'b/n)
+ *   memory    alpha_i is one scalar per sample, the last phi' seen for row i,
+ *             so f'_i - alpha_i = (phi'(a_i.x) - alpha_i) a_i  (Section 2 footnote on
+ *                                                              linear models; App. G)
+ *   update    x+ = x - gamma (f'_i(x) - alpha_i + D_i abar + lambda D_i x)
+ *             with D = diag(1/p_v), p_v = #{i : v in S_i} / n, D_i = P_{S_i} D
+ *                                                             (Section 2, Eq. SparseSAGA;
+ *                                                              Section 4.2 "Exact regularization")
+ *             abar += (delta/n) a_i,  alpha_i += delta         (Algorithm 2, shared-memory
+ *                                                              updates; serial here)
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - x0 = 0, alpha0 = 0, abar0 = 0 (the Section 2 footnote lets the memory
+ *     start at any value; zero is the usual choice).
+ *   - S_i is the structural support of row i (its stored entries); a column
+ *     no row touches gets D_v = 0 and keeps x_v = 0, its optimum.
+ *   - Within an update, x_v and abar_v are read before any write (Algorithm 2
+ *     reads before it writes); the lambda term uses that same read of x_v.
+ *   - L = c max_i ||a_i||^2 + lambda with c = 1/4 (logistic), 1 (squared);
+ *     gamma = min(1/(3L), 1/(lambda max_v D_v)).
+ *   - Samples i_t come from a counter-based stream: SplitMix64 (Steele, Lea &
+ *     Flood 2014) of state seed + (t+1) * 0x9E3779B97F4A7C15, mapped to
+ *     [0, n) by the high 64 bits of the 128-bit product with n (Lemire).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_LOGISTIC 0
+#define ORACLE_SQUARED 1
+
+/* ------------------------------------------------------------------ */
+/* sample stream                                                       */
+/* ------------------------------------------------------------------ */
+
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t t) {
+    uint64_t z = seed + (t + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+int64_t oracle_sample(uint64_t seed, uint64_t t, int64_t n) {
+    unsigned __int128 prod = (unsigned __int128)oracle_splitmix64(seed, t) * (unsigned __int128)(uint64_t)n;
+    return (int64_t)(uint64_t)(prod >> 64);
+}
+
+void oracle_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, int64_t* out) {
+    for (int64_t s = 0; s < count; ++s) out[s] = oracle_sample(seed, t0 + (uint64_t)s, n);
+}
+
+/* ------------------------------------------------------------------ */
+/* per-sample loss and its derivative in z = a_i . x                   */
+/* ------------------------------------------------------------------ */
+
+double oracle_phi(double z, double b, int loss) {
+    if (loss == ORACLE_SQUARED) return 0.5 * (z - b) * (z - b);
+    double m = b * z; /* log(1 + exp(-m)) */
+    if (m > 0.0) return log1p(exp(-m));
+    return -m + log1p(exp(m));
+}
+
+double oracle_dphi(double z, double b, int loss) {
+    if (loss == ORACLE_SQUARED) return z - b;
+    double m = b * z; /* d/dz log(1 + exp(-b z)) = -b / (1 + exp(b z)) */
+    if (m > 0.0) {
+        double e = exp(-m);
+        return -b * e / (1.0 + e);
+    }
+    return -b / (1.0 + exp(m));
+}
+
+/* ------------------------------------------------------------------ */
+/* p_v, D, L, gamma                                                    */
+/* ------------------------------------------------------------------ */
+
+/* cnt_v = #{i : v in S_i}  (so p_v = cnt_v / n; Section 2) */
+void oracle_column_counts(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, int64_t* cnt) {
+    memset(cnt, 0, (size_t)d * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) cnt[colidx[k]] += 1;
+}
+
+/* D_v = 1 / p_v = n / cnt_v, 0 for untouched columns (Section 2) */
+void oracle_reweighting(int64_t n, int64_t d, const int64_t* cnt, double* D) {
+    for (int64_t v = 0; v < d; ++v) D[v] = cnt[v] > 0 ? (double)n / (double)cnt[v] : 0.0;
+}
+
+double oracle_smoothness(int64_t n, const int64_t* rowptr, const double* val, int loss, double lambda) {
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) s += val[k] * val[k];
+        if (s > mx) mx = s;
+    }
+    return (loss == ORACLE_LOGISTIC ? 0.25 : 1.0) * mx + lambda;
+}
+
+double oracle_step_size(double L, double lambda, int64_t d, const double* D) {
+    double dmax = 0.0;
+    for (int64_t v = 0; v < d; ++v)
+        if (D[v] > dmax) dmax = D[v];
+    double g = 1.0 / (3.0 * L);
+    if (lambda * dmax > 0.0 && 1.0 / (lambda * dmax) < g) g = 1.0 / (lambda * dmax);
+    return g;
+}
+
+/* ------------------------------------------------------------------ */
+/* the Sparse SAGA iteration                                           */
+/* ------------------------------------------------------------------ */
+
+/* One Sparse SAGA update on sample i, in place on (x, alpha, abar).
+ * Returns delta = phi'(a_i . x) - alpha_i. */
+static double sparse_saga_update(int64_t i, int64_t n, const int64_t* rowptr, const int32_t* colidx,
+                                 const double* val, const double* b, int loss, double lambda,
+                                 const double* D, double gamma, double* x, double* alpha, double* abar) {
+    int64_t s = rowptr[i], e = rowptr[i + 1];
+    /* read x on S_i, form the dot product */
+    double z = 0.0;
+    for (int64_t k = s; k < e; ++k) z += val[k] * x[colidx[k]];
+    /* scalar gradient and its change against the stored memory */
+    double delta = oracle_dphi(z, b[i], loss) - alpha[i];
+    /* per-coordinate step and running-average update on S_i */
+    for (int64_t k = s; k < e; ++k) {
+        int32_t v = colidx[k];
+        double xo = x[v];
+        double ab = abar[v];
+        x[v] = xo - gamma * (delta * val[k] + D[v] * (ab + lambda * xo));
+        abar[v] = ab + delta * val[k] / (double)n;
+    }
+    alpha[i] = alpha[i] + delta;
+    return delta;
+}
+
+/* Updates on an explicit list of samples idx[0..count). */
+int oracle_saga_indices(int64_t n, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                        const double* b, int loss, double lambda, const double* D, double gamma,
+                        const int64_t* idx, int64_t count, double* x, double* alpha, double* abar) {
+    for (int64_t s = 0; s < count; ++s) {
+        if (idx[s] < 0 || idx[s] >= n) return -1;
+        sparse_saga_update(idx[s], n, rowptr, colidx, val, b, loss, lambda, D, gamma, x, alpha, abar);
+    }
+    return 0;
+}
+
+/* Updates t = t0 .. t0+count-1 of the seeded sample stream. */
+int oracle_saga_run(int64_t n, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                    const double* b, int loss, double lambda, const double* D, double gamma,
+                    uint64_t seed, uint64_t t0, int64_t count, double* x, double* alpha, double* abar) {
+    for (int64_t s = 0; s < count; ++s) {
+        int64_t i = oracle_sample(seed, t0 + (uint64_t)s, n);
+        sparse_saga_update(i, n, rowptr, colidx, val, b, loss, lambda, D, gamma, x, alpha, abar);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* objective and gradient, Neumaier-compensated sums                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct { double s, c; } ksum;
+
+static inline void kadd(ksum* a, double v) {
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+/* f(x) = (1/n) sum_i phi(a_i . x; b_i) + (lambda/2) ||x||^2   (Section 4.1) */
+double oracle_objective(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                        const double* b, int loss, double lambda, const double* x) {
+    ksum data = {0.0, 0.0}, reg = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        ksum z = {0.0, 0.0};
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kadd(&z, val[k] * x[colidx[k]]);
+        kadd(&data, oracle_phi(z.s + z.c, b[i], loss));
+    }
+    for (int64_t v = 0; v < d; ++v) kadd(&reg, x[v] * x[v]);
+    return (data.s + data.c) / (double)n + 0.5 * lambda * (reg.s + reg.c);
+}
+
+/* grad f(x) = (1/n) sum_i phi'(a_i . x; b_i) a_i + lambda x */
+int oracle_gradient(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                    const double* b, int loss, double lambda, const double* x, double* g) {
+    ksum* acc = (ksum*)calloc((size_t)d, sizeof(ksum));
+    if (!acc) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        ksum z = {0.0, 0.0};
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kadd(&z, val[k] * x[colidx[k]]);
+        double gi = oracle_dphi(z.s + z.c, b[i], loss);
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kadd(&acc[colidx[k]], gi * val[k]);
+    }
+    for (int64_t v = 0; v < d; ++v) g[v] = (acc[v].s + acc[v].c) / (double)n + lambda * x[v];
+    free(acc);
+    return 0;
+}
+
+/* (1/n) sum_i alpha_i a_i, compensated: what abar must equal at all times. */
+int oracle_memory_average(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx,
+                          const double* val, const double* alpha, double* out) {
+    ksum* acc = (ksum*)calloc((size_t)d, sizeof(ksum));
+    if (!acc) return -2;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) kadd(&acc[colidx[k]], alpha[i] * val[k]);
+    for (int64_t v = 0; v < d; ++v) out[v] = (acc[v].s + acc[v].c) / (double)n;
+    free(acc);
+    return 0;
+}
