@@ -11,8 +11,9 @@ available, so each generator stands in for one of them with the same shape
 
 * ``config1``  tiny logistic instance (2,000 x 500, 25 uniform columns/row).
 * ``config2``  RCV1-like: 700,000 x 47,000, Poisson(75) distinct Zipf(1.1)
-  columns per row, lognormal(0,1) values, rows L2-normalised, planted labels
-  with 10% flips.
+  columns per row, TF-IDF-like values (lognormal(0,1) term weight times the
+  smooth inverse document frequency ln((1+n)/(1+df_v)) + 1 of the column),
+  rows L2-normalised, planted labels with 10% flips.
 * ``config3``  Covtype-like least squares: 581,000 x 54, ten standardised
   Gaussian columns plus one-hot blocks of 4 and 40 columns (12 nnz/row),
   targets a.w* + N(0, 0.1^2).
@@ -167,14 +168,18 @@ def config1(seed: int = 0, n: int = 2000, d: int = 500, k: int = 25) -> Problem:
 
 def config2(seed: int = 0, n: int = 700_000, d: int = 47_000, mean_nnz: float = 75.0,
             zipf_s: float = 1.1) -> Problem:
-    """RCV1-like logistic instance (see module docstring)."""
+    """RCV1-like logistic instance (see module docstring).  Frequent columns
+    get small weights, as term weighting does in text data."""
     counts = np.maximum(1, _rng(seed, _T_COUNTS).poisson(mean_nnz, size=n))
     perm = _rng(seed, _T_PERM).permutation(d).astype(np.int32)
     rowptr, colidx = _distinct_supports(seed, n, d, counts, _zipf_cdf(d, zipf_s), perm)
-    val = _row_normalise(rowptr, _rng(seed, _T_VALUES).lognormal(0.0, 1.0, size=len(colidx)))
+    tf = _rng(seed, _T_VALUES).lognormal(0.0, 1.0, size=len(colidx))
+    df = np.bincount(colidx, minlength=d)
+    idf = np.log((1.0 + n) / (1.0 + df)) + 1.0
+    val = _row_normalise(rowptr, tf * idf[colidx])
     b = _planted_labels(seed, rowptr, colidx, val, d, 0.10)
     return Problem("config2", n, d, rowptr, colidx, val, b, LOGISTIC, 1.0 / n,
-                   meta={"zipf_s": zipf_s, "mean_nnz": mean_nnz})
+                   meta={"zipf_s": zipf_s, "mean_nnz": mean_nnz, "values": "lognormal tf x smooth idf"})
 
 
 def config3(seed: int = 0, n: int = 581_000, lam: float = 1e-4) -> Problem:

@@ -1,0 +1,348 @@
+"""Python binding of the gfx950 Sparse SAGA / ASAGA library (libasaga.so).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in ``include/asaga.h``.  The functions below carry
+the C names; ``Solver`` bundles them for one context.  Inputs may be numpy
+arrays (host memory, copied by the library) or torch CUDA tensors (device
+memory, borrowed); torch is used for nothing else than device memory and
+streams.
+
+If the library has not been built this module raises ImportError: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libasaga.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                      "(python -m paper_1606_04809_amd.build, or __graft_entry__.build())")
+
+# One HIP runtime per process: torch ships its own libamdhip64 (same SONAME
+# as the system one).  Loading torch first lets the dynamic loader resolve
+# this library's HIP dependency to the runtime torch already mapped, so that
+# device pointers and streams are shared instead of split across two runtimes.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the library itself does not need torch
+    pass
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants (asaga.h) ----------------------------------------------------
+ASAGA_OK = 0
+ASAGA_E_ARG = -1
+ASAGA_E_CSR = -2
+ASAGA_E_OOM = -3
+ASAGA_E_HIP = -4
+ASAGA_E_DIVERGED = -5
+ASAGA_E_STATE = -6
+ASAGA_LOSS_LOGISTIC = 0
+ASAGA_LOSS_SQUARED = 1
+ASAGA_VAL_F64 = 0
+ASAGA_VAL_F32 = 1
+ASAGA_VAL_BF16 = 2
+ASAGA_MEM_HOST = 0
+ASAGA_MEM_DEVICE = 1
+ASAGA_MODE_SERIAL = 0
+ASAGA_MODE_ASYNC = 1
+ASAGA_PREC_F64 = 0
+ASAGA_PREC_MIXED = 1
+
+ERROR_NAMES = {0: "ASAGA_OK", -1: "ASAGA_E_ARG", -2: "ASAGA_E_CSR", -3: "ASAGA_E_OOM", -4: "ASAGA_E_HIP",
+               -5: "ASAGA_E_DIVERGED", -6: "ASAGA_E_STATE"}
+
+
+class asaga_problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("colidx", ctypes.c_void_p), ("val", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("lam", ctypes.c_double), ("val_dtype", ctypes.c_int32), ("loss", ctypes.c_int32),
+                ("mem", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class asaga_opts(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_double), ("seed", ctypes.c_uint64), ("mode", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("waves", ctypes.c_int32), ("lanes_per_sample", ctypes.c_int32),
+                ("racy", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3), ("stream", ctypes.c_void_p)]
+
+
+class asaga_batch(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("reserved", ctypes.c_int32), ("row_fold", ctypes.c_void_p),
+                ("inst_fold", ctypes.c_void_p), ("inst_lambda", ctypes.c_void_p)]
+
+
+class asaga_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("delta_r", ctypes.c_int64), ("t", ctypes.c_int64), ("L", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("lam", ctypes.c_double), ("waves", ctypes.c_int32),
+                ("lanes_per_sample", ctypes.c_int32), ("n_inst", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_CTX = ctypes.c_void_p
+_SIGS = {
+    "asaga_init": (ctypes.c_int, [ctypes.POINTER(_CTX), ctypes.POINTER(asaga_problem), ctypes.POINTER(asaga_opts)]),
+    "asaga_init_batched": (ctypes.c_int, [ctypes.POINTER(_CTX), ctypes.POINTER(asaga_problem),
+                                          ctypes.POINTER(asaga_opts), ctypes.POINTER(asaga_batch)]),
+    "asaga_epochs": (ctypes.c_int, [_CTX, ctypes.c_int64]),
+    "asaga_updates": (ctypes.c_int, [_CTX, ctypes.c_int64]),
+    "asaga_objective": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "asaga_full_grad": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P]),
+    "asaga_get_x": (ctypes.c_int, [_CTX, ctypes.c_int32, _P]),
+    "asaga_get_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "asaga_set_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "asaga_reanchor": (ctypes.c_int, [_CTX]),
+    "asaga_info_get": (ctypes.c_int, [_CTX, ctypes.POINTER(asaga_info)]),
+    "asaga_sync": (ctypes.c_int, [_CTX]),
+    "asaga_sample_stream": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "asaga_last_error": (ctypes.c_char_p, [_CTX]),
+    "asaga_free": (None, [_CTX]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+def hip_runtimes_loaded() -> list[str]:
+    """Paths of the libamdhip64 copies mapped into this process (one is
+    expected)."""
+    paths = set()
+    with open("/proc/self/maps") as fh:
+        for line in fh:
+            if "libamdhip64" in line:
+                paths.add(line.split()[-1])
+    return sorted(paths)
+
+
+class AsagaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, ctx=None):
+    if rc != ASAGA_OK:
+        raise AsagaError(rc, asaga_last_error(ctx))
+    return rc
+
+
+# ---- the C functions, same names ---------------------------------------------
+def asaga_init(prob: asaga_problem, opts: asaga_opts):
+    ctx = _CTX()
+    _check(_lib.asaga_init(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts)))
+    return ctx
+
+
+def asaga_init_batched(prob: asaga_problem, opts: asaga_opts, batch: asaga_batch):
+    ctx = _CTX()
+    _check(_lib.asaga_init_batched(ctypes.byref(ctx), ctypes.byref(prob), ctypes.byref(opts), ctypes.byref(batch)))
+    return ctx
+
+
+def asaga_epochs(ctx, n_epochs: int):
+    return _check(_lib.asaga_epochs(ctx, int(n_epochs)), ctx)
+
+
+def asaga_updates(ctx, count: int):
+    return _check(_lib.asaga_updates(ctx, int(count)), ctx)
+
+
+def _host_f64(x, size):
+    if x is None:
+        return None, None
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    if a.shape != (size,):
+        raise ValueError(f"expected a vector of length {size}")
+    return a, a.ctypes.data
+
+
+def asaga_objective(ctx, inst: int, d: int, x=None) -> float:
+    keep, px = _host_f64(x, d)
+    f = ctypes.c_double()
+    _check(_lib.asaga_objective(ctx, int(inst), px, ctypes.byref(f)), ctx)
+    return f.value
+
+
+def asaga_full_grad(ctx, inst: int, d: int, x=None) -> np.ndarray:
+    keep, px = _host_f64(x, d)
+    g = np.empty(d)
+    _check(_lib.asaga_full_grad(ctx, int(inst), px, g.ctypes.data), ctx)
+    return g
+
+
+def asaga_get_x(ctx, inst: int, d: int) -> np.ndarray:
+    x = np.empty(d)
+    _check(_lib.asaga_get_x(ctx, int(inst), x.ctypes.data), ctx)
+    return x
+
+
+def asaga_get_state(ctx, inst: int, d: int, m: int):
+    x, alpha, abar = np.empty(d), np.empty(m), np.empty(d)
+    t = ctypes.c_int64()
+    _check(_lib.asaga_get_state(ctx, int(inst), x.ctypes.data, alpha.ctypes.data, abar.ctypes.data, ctypes.byref(t)),
+           ctx)
+    return x, alpha, abar, int(t.value)
+
+
+def asaga_set_state(ctx, inst: int, d: int, m: int, x=None, alpha=None, abar=None, t=None):
+    kx, px = _host_f64(x, d)
+    ka, pa = _host_f64(alpha, m)
+    kb, pb = _host_f64(abar, d)
+    tt = ctypes.c_int64(int(t)) if t is not None else None
+    _check(_lib.asaga_set_state(ctx, int(inst), px, pa, pb, ctypes.byref(tt) if tt is not None else None), ctx)
+
+
+def asaga_reanchor(ctx):
+    return _check(_lib.asaga_reanchor(ctx), ctx)
+
+
+def asaga_info_get(ctx) -> asaga_info:
+    info = asaga_info()
+    _check(_lib.asaga_info_get(ctx, ctypes.byref(info)), ctx)
+    return info
+
+
+def asaga_sync(ctx):
+    return _check(_lib.asaga_sync(ctx), ctx)
+
+
+def asaga_sample_stream(seed: int, t0: int, count: int, n: int) -> np.ndarray:
+    out = np.empty(count, dtype=np.int64)
+    _check(_lib.asaga_sample_stream(int(seed), int(t0), int(count), int(n), out.ctypes.data))
+    return out
+
+
+def asaga_last_error(ctx=None) -> str:
+    s = _lib.asaga_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def asaga_free(ctx):
+    _lib.asaga_free(ctx)
+
+
+# ---- one context -------------------------------------------------------------
+def _is_torch_cuda(a) -> bool:
+    return type(a).__module__.startswith("torch") and getattr(a, "is_cuda", False)
+
+
+class Solver:
+    """One library context over a CSR problem.
+
+    ``rowptr`` int64[n+1], ``colidx`` int32[nnz], ``val`` float64/float32
+    or bfloat16 bit patterns (uint16, with ``val_dtype=ASAGA_VAL_BF16``),
+    ``b`` float64[n].  All four are numpy arrays (copied to the device) or
+    all four are torch CUDA tensors (borrowed; this object keeps them
+    alive).  ``stream`` is a torch.cuda.Stream or a raw hipStream_t integer.
+    """
+
+    def __init__(self, n, d, rowptr, colidx, val, b, lam, loss=ASAGA_LOSS_LOGISTIC, val_dtype=None,
+                 mode=ASAGA_MODE_SERIAL, precision=ASAGA_PREC_F64, step=0.0, seed=0, waves=0,
+                 lanes_per_sample=0, racy=0, stream=None, batch=None):
+        self.n, self.d = int(n), int(d)
+        arrays = (rowptr, colidx, val, b)
+        on_dev = [_is_torch_cuda(a) for a in arrays]
+        if any(on_dev) and not all(on_dev):
+            raise ValueError("problem arrays must all be numpy arrays or all be torch CUDA tensors")
+        if all(on_dev):
+            mem = ASAGA_MEM_DEVICE
+            self._keep = arrays
+            ptrs = [a.data_ptr() for a in arrays]
+            if val_dtype is None:
+                val_dtype = {8: ASAGA_VAL_F64, 4: ASAGA_VAL_F32, 2: ASAGA_VAL_BF16}[val.element_size()]
+        else:
+            mem = ASAGA_MEM_HOST
+            rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+            colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+            if val_dtype is None:
+                val_dtype = {np.dtype(np.float64): ASAGA_VAL_F64, np.dtype(np.float32): ASAGA_VAL_F32,
+                             np.dtype(np.uint16): ASAGA_VAL_BF16}[np.asarray(val).dtype]
+            vdt = {ASAGA_VAL_F64: np.float64, ASAGA_VAL_F32: np.float32, ASAGA_VAL_BF16: np.uint16}[val_dtype]
+            val = np.ascontiguousarray(val, dtype=vdt)
+            b = np.ascontiguousarray(b, dtype=np.float64)
+            self._keep = (rowptr, colidx, val, b)
+            ptrs = [a.ctypes.data for a in self._keep]
+        self.prob = asaga_problem(self.n, self.d, *ptrs, float(lam), int(val_dtype), int(loss), mem, 0)
+        if stream is not None and not isinstance(stream, int):
+            stream = stream.cuda_stream
+        self.opts = asaga_opts(float(step), int(seed), int(mode), int(precision), int(waves), int(lanes_per_sample),
+                               int(racy), (ctypes.c_int32 * 3)(0, 0, 0), stream)
+        if batch is None:
+            self.ctx = asaga_init(self.prob, self.opts)
+            self.n_inst = 1
+        else:
+            row_fold, inst_fold, inst_lambda = batch
+            self._bkeep = (None if row_fold is None else np.ascontiguousarray(row_fold, dtype=np.int8),
+                           np.ascontiguousarray(inst_fold, dtype=np.int32),
+                           np.ascontiguousarray(inst_lambda, dtype=np.float64))
+            rf, inf_, il = self._bkeep
+            bt = asaga_batch(len(inf_), 0, None if rf is None else rf.ctypes.data, inf_.ctypes.data, il.ctypes.data)
+            self.ctx = asaga_init_batched(self.prob, self.opts, bt)
+            self.n_inst = len(inf_)
+
+    # marshalling wrappers
+    def epochs(self, e: int):
+        asaga_epochs(self.ctx, e)
+
+    def updates(self, count: int):
+        asaga_updates(self.ctx, count)
+
+    def objective(self, inst: int = 0, x=None) -> float:
+        return asaga_objective(self.ctx, inst, self.d, x)
+
+    def full_grad(self, inst: int = 0, x=None) -> np.ndarray:
+        return asaga_full_grad(self.ctx, inst, self.d, x)
+
+    def get_x(self, inst: int = 0) -> np.ndarray:
+        return asaga_get_x(self.ctx, inst, self.d)
+
+    def get_state(self, inst: int = 0, m: int | None = None):
+        return asaga_get_state(self.ctx, inst, self.d, self.n if m is None else m)
+
+    def set_state(self, inst: int = 0, m: int | None = None, **kw):
+        asaga_set_state(self.ctx, inst, self.d, self.n if m is None else m, **kw)
+
+    def reanchor(self):
+        asaga_reanchor(self.ctx)
+
+    def info(self) -> asaga_info:
+        return asaga_info_get(self.ctx)
+
+    def sync(self):
+        asaga_sync(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            asaga_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def from_problem(p, **kw) -> Solver:
+    """Solver over a ``datagen.Problem``-like object (n, d, rowptr, colidx,
+    val, b, loss, lam; optional val_bf16).  ``bf16=True`` passes the stored
+    bfloat16 values instead of the float64 ones."""
+    bf16 = kw.pop("bf16", False)
+    val = p.val_bf16 if bf16 else p.val
+    vdt = ASAGA_VAL_BF16 if bf16 else None
+    return Solver(p.n, p.d, p.rowptr, p.colidx, val, p.b, p.lam, loss=p.loss, val_dtype=vdt, **kw)

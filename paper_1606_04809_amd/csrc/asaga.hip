@@ -1,0 +1,705 @@
+// C ABI of the gfx950 Sparse SAGA / ASAGA library (declared in asaga.h):
+// validation, device memory, the step-size rule, launches, read-back.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "asaga.h"
+#include "internal.hpp"
+
+using namespace asaga;
+
+namespace {
+
+thread_local std::string g_init_error = "no error";
+
+struct Inst {
+    int64_t m = 0;
+    int32_t* rows = nullptr;  // device, nullptr = identity
+    double lambda = 0.0, gamma = 0.0, L = 0.0;
+    int64_t delta_r = 0;
+    int32_t cnt_min = 0;
+    int32_t* cnt = nullptr;
+    double* D = nullptr;
+    void* x = nullptr;
+    void* alpha = nullptr;
+    double* abar = nullptr;
+    uint64_t seed = 0;
+    int64_t t = 0;
+};
+
+}  // namespace
+
+struct asaga_ctx {
+    int64_t n = 0, d = 0, nnz = 0;
+    int32_t loss = 0, val_dtype = 0;
+    bool own = false;
+    int64_t* rowptr = nullptr;
+    int32_t* colidx = nullptr;
+    void* val = nullptr;
+    double* b = nullptr;
+    asaga_opts o{};
+    hipStream_t st = nullptr;
+    bool mixed = false;
+    int lanes = 64, waves = 1, waves_per_inst = 0;
+    std::vector<Inst> inst;
+    InstArgs* d_insts = nullptr;
+    std::vector<void*> allocs;
+    // scratch
+    double* z = nullptr;      // [n]
+    double* tmp = nullptr;    // [n]
+    double* vecd = nullptr;   // [d]
+    double* xin = nullptr;    // [d]
+    double* part = nullptr;   // [kSumParts]
+    double* scal = nullptr;   // [4]
+    int* flag = nullptr;      // [1]
+    int32_t* stats = nullptr; // [2]
+    unsigned long long* maxbits = nullptr;
+    std::string err = "no error";
+};
+
+namespace {
+
+int fail(asaga_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_init_error = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? ASAGA_E_OOM : ASAGA_E_HIP,              \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+template <typename T>
+int dalloc(asaga_ctx* c, T** p, int64_t count) {
+    void* q = nullptr;
+    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, e == hipErrorOutOfMemory ? ASAGA_E_OOM : ASAGA_E_HIP,
+                    "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    }
+    c->allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return ASAGA_OK;
+}
+
+size_t val_size(int32_t dt) { return dt == ASAGA_VAL_F64 ? 8 : dt == ASAGA_VAL_F32 ? 4 : 2; }
+
+double host_val(const void* v, int32_t dt, int64_t k) {
+    if (dt == ASAGA_VAL_F64) return static_cast<const double*>(v)[k];
+    if (dt == ASAGA_VAL_F32) return static_cast<const float*>(v)[k];
+    uint32_t bits = (uint32_t) static_cast<const uint16_t*>(v)[k] << 16;
+    float f;
+    std::memcpy(&f, &bits, 4);
+    return f;
+}
+
+// Host-side checks of a problem in host memory (before any device work).
+int validate_host(const asaga_problem* p) {
+    const int64_t n = p->n, d = p->d;
+    if (p->rowptr[0] != 0) return fail(nullptr, ASAGA_E_CSR, "rowptr[0] != 0");
+    const int64_t nnz = p->rowptr[n];
+    if (nnz < n) return fail(nullptr, ASAGA_E_CSR, "rowptr[n] < n: some row is empty");
+    if (nnz > (int64_t)1 << 40) return fail(nullptr, ASAGA_E_CSR, "nnz too large");
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t s = p->rowptr[i], e = p->rowptr[i + 1];
+        if (e < s || e > nnz) return fail(nullptr, ASAGA_E_CSR, "rowptr decreasing at row " + std::to_string(i));
+        if (e == s) return fail(nullptr, ASAGA_E_CSR, "row " + std::to_string(i) + " is empty");
+        int64_t prev = -1;
+        for (int64_t k = s; k < e; ++k) {
+            const int64_t c = p->colidx[k];
+            if (c < 0 || c >= d) return fail(nullptr, ASAGA_E_CSR, "column index out of range in row " + std::to_string(i));
+            if (c <= prev)
+                return fail(nullptr, ASAGA_E_CSR, "columns not strictly increasing in row " + std::to_string(i));
+            prev = c;
+            if (!std::isfinite(host_val(p->val, p->val_dtype, k)))
+                return fail(nullptr, ASAGA_E_CSR, "non-finite value in row " + std::to_string(i));
+        }
+        const double b = p->b[i];
+        if (!std::isfinite(b)) return fail(nullptr, ASAGA_E_CSR, "non-finite label at row " + std::to_string(i));
+        if (p->loss == ASAGA_LOSS_LOGISTIC && b != 1.0 && b != -1.0)
+            return fail(nullptr, ASAGA_E_CSR, "logistic label not in {-1,+1} at row " + std::to_string(i));
+    }
+    return ASAGA_OK;
+}
+
+int check_args(const asaga_problem* p, const asaga_opts* o) {
+    if (!p || !o) return fail(nullptr, ASAGA_E_ARG, "NULL problem or options");
+    if (p->n < 1 || p->d < 1 || p->d > INT32_MAX || p->n > INT32_MAX)
+        return fail(nullptr, ASAGA_E_ARG, "n and d must be in [1, 2^31)");
+    if (!p->rowptr || !p->colidx || !p->val || !p->b) return fail(nullptr, ASAGA_E_ARG, "NULL problem array");
+    if (p->val_dtype < ASAGA_VAL_F64 || p->val_dtype > ASAGA_VAL_BF16)
+        return fail(nullptr, ASAGA_E_ARG, "bad val_dtype");
+    if (p->loss != ASAGA_LOSS_LOGISTIC && p->loss != ASAGA_LOSS_SQUARED) return fail(nullptr, ASAGA_E_ARG, "bad loss");
+    if (p->mem != ASAGA_MEM_HOST && p->mem != ASAGA_MEM_DEVICE) return fail(nullptr, ASAGA_E_ARG, "bad mem");
+    if (p->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "problem.reserved must be 0");
+    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(nullptr, ASAGA_E_ARG, "lambda must be > 0 and finite");
+    if (o->mode != ASAGA_MODE_SERIAL && o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "bad mode");
+    if (o->precision != ASAGA_PREC_F64 && o->precision != ASAGA_PREC_MIXED)
+        return fail(nullptr, ASAGA_E_ARG, "bad precision");
+    if (!std::isfinite(o->step)) return fail(nullptr, ASAGA_E_ARG, "step must be finite");
+    if (o->waves < 0 || o->waves > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "waves out of range");
+    if (o->lanes_per_sample != 0 && o->lanes_per_sample != 8 && o->lanes_per_sample != 16 &&
+        o->lanes_per_sample != 32 && o->lanes_per_sample != 64)
+        return fail(nullptr, ASAGA_E_ARG, "lanes_per_sample must be 0, 8, 16, 32 or 64");
+    if (o->racy != 0 && o->racy != 1) return fail(nullptr, ASAGA_E_ARG, "racy must be 0 or 1");
+    if (o->racy && o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "racy applies to async mode only");
+    for (int r = 0; r < 3; ++r)
+        if (o->reserved[r] != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
+    return ASAGA_OK;
+}
+
+MatArgs mat(const asaga_ctx* c) {
+    MatArgs A;
+    A.rowptr = c->rowptr;
+    A.colidx = c->colidx;
+    A.val = c->val;
+    A.b = c->b;
+    A.n = c->n;
+    A.d = c->d;
+    A.val_dtype = c->val_dtype;
+    A.loss = c->loss;
+    return A;
+}
+
+InstArgs inst_args(const asaga_ctx* c, const Inst& I, uint64_t t0, uint64_t count) {
+    InstArgs a;
+    a.rows = I.rows;
+    a.x = I.x;
+    a.alpha = I.alpha;
+    a.abar = I.abar;
+    a.D = I.D;
+    a.m = I.m;
+    a.gamma = I.gamma;
+    a.lambda = I.lambda;
+    a.inv_m = 1.0 / (double)I.m;
+    a.seed = I.seed;
+    a.t0 = t0;
+    a.count = count;
+    (void)c;
+    return a;
+}
+
+int zero_state(asaga_ctx* c, Inst& I) {
+    if (c->mixed) {
+        HIPCHK(c, launch_fill_f32(static_cast<float*>(I.x), 0.0f, c->d, c->st));
+        HIPCHK(c, launch_fill_f32(static_cast<float*>(I.alpha), 0.0f, I.m, c->st));
+    } else {
+        HIPCHK(c, launch_fill_f64(static_cast<double*>(I.x), 0.0, c->d, c->st));
+        HIPCHK(c, launch_fill_f64(static_cast<double*>(I.alpha), 0.0, I.m, c->st));
+    }
+    HIPCHK(c, launch_fill_f64(I.abar, 0.0, c->d, c->st));
+    I.t = 0;
+    return ASAGA_OK;
+}
+
+// Column counts, D, Delta_r, L and gamma of one instance; zero its state.
+int setup_instance(asaga_ctx* c, Inst& I) {
+    int rc;
+    const size_t xs = c->mixed ? 4 : 8;
+    if ((rc = dalloc(c, &I.cnt, c->d))) return rc;
+    if ((rc = dalloc(c, &I.D, c->d))) return rc;
+    if ((rc = dalloc(c, &I.abar, c->d))) return rc;
+    char* xp = nullptr;
+    if ((rc = dalloc(c, &xp, c->d * (int64_t)xs))) return rc;
+    I.x = xp;
+    char* ap = nullptr;
+    if ((rc = dalloc(c, &ap, I.m * (int64_t)xs))) return rc;
+    I.alpha = ap;
+
+    const MatArgs A = mat(c);
+    HIPCHK(c, launch_fill_i32(I.cnt, 0, c->d, c->st));
+    HIPCHK(c, launch_colcount(A, I.rows, I.m, I.cnt, c->st));
+    const int32_t init_stats[2] = {0, 0x7fffffff};
+    HIPCHK(c, hipMemcpyAsync(c->stats, init_stats, sizeof(init_stats), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, launch_reweight(I.cnt, c->d, I.m, I.D, c->stats, c->st));
+    const unsigned long long zero = 0;
+    HIPCHK(c, hipMemcpyAsync(c->maxbits, &zero, sizeof(zero), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, launch_rownorm_max(A, I.rows, I.m, c->maxbits, c->st));
+    int32_t stats[2];
+    unsigned long long bits = 0;
+    HIPCHK(c, hipMemcpyAsync(stats, c->stats, sizeof(stats), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(&bits, c->maxbits, sizeof(bits), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    double maxnorm;
+    std::memcpy(&maxnorm, &bits, 8);
+    I.delta_r = stats[0];
+    I.cnt_min = stats[1];
+    I.L = (c->loss == ASAGA_LOSS_LOGISTIC ? 0.25 : 1.0) * maxnorm + I.lambda;
+    if (c->o.step > 0.0) {
+        I.gamma = c->o.step;
+    } else {
+        // gamma = min(1/(3L), 1/(lambda max_v D_v)); max_v D_v = m / min positive count
+        const double dmax = stats[1] > 0 && stats[1] != 0x7fffffff ? (double)I.m / (double)stats[1] : 0.0;
+        double g = 1.0 / (3.0 * I.L);
+        if (I.lambda * dmax > 0.0 && 1.0 / (I.lambda * dmax) < g) g = 1.0 / (I.lambda * dmax);
+        I.gamma = g;
+    }
+    return zero_state(c, I);
+}
+
+void pick_shape(asaga_ctx* c) {
+    const double mean = (double)c->nnz / (double)c->n;
+    int lanes = c->o.lanes_per_sample;
+    if (lanes == 0) {
+        // half the largest power of two not above the mean row length, in [8, 64]
+        int p = 1;
+        while (p * 2 <= mean && p < 128) p *= 2;
+        lanes = p / 2;
+        if (lanes < 8) lanes = 8;
+        if (lanes > 64) lanes = 64;
+    }
+    c->lanes = lanes;
+    int waves = c->o.waves;
+    if (waves == 0) {
+        int cus = device_cu_count();
+        if (cus <= 0) cus = 256;
+        waves = cus * 16;
+    }
+    c->waves = waves;
+}
+
+int free_all(asaga_ctx* c) {
+    if (!c) return ASAGA_OK;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    for (void* p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    return ASAGA_OK;
+}
+
+int check_flag(asaga_ctx* c) {
+    int f = 0;
+    HIPCHK(c, hipMemcpyAsync(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (f) return fail(c, ASAGA_E_DIVERGED, "a non-finite gradient change appeared during the updates");
+    return ASAGA_OK;
+}
+
+int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, const asaga_batch* bt) {
+    if (!out) return fail(nullptr, ASAGA_E_ARG, "NULL output pointer");
+    *out = nullptr;
+    int rc = check_args(p, o);
+    if (rc) return rc;
+    if (bt) {
+        if (bt->n_inst < 1 || bt->n_inst > 65536 || !bt->inst_fold || !bt->inst_lambda || bt->reserved != 0)
+            return fail(nullptr, ASAGA_E_ARG, "bad batch descriptor");
+        if (o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "batched solves run in async mode");
+        if (o->racy) return fail(nullptr, ASAGA_E_ARG, "racy is not available for batched solves");
+        for (int k = 0; k < bt->n_inst; ++k) {
+            if (!(bt->inst_lambda[k] > 0.0) || !std::isfinite(bt->inst_lambda[k]))
+                return fail(nullptr, ASAGA_E_ARG, "instance lambda must be > 0 and finite");
+            if (bt->inst_fold[k] < -1 || bt->inst_fold[k] > 127) return fail(nullptr, ASAGA_E_ARG, "bad inst_fold");
+            if (bt->inst_fold[k] >= 0 && !bt->row_fold) return fail(nullptr, ASAGA_E_ARG, "row_fold is NULL");
+        }
+    }
+    if (p->mem == ASAGA_MEM_HOST) {
+        rc = validate_host(p);
+        if (rc) return rc;
+    }
+
+    asaga_ctx* c = new (std::nothrow) asaga_ctx();
+    if (!c) return fail(nullptr, ASAGA_E_OOM, "host allocation failed");
+    c->o = *o;
+    c->st = static_cast<hipStream_t>(o->stream);
+    c->n = p->n;
+    c->d = p->d;
+    c->loss = p->loss;
+    c->val_dtype = p->val_dtype;
+    c->mixed = o->precision == ASAGA_PREC_MIXED;
+
+    auto bail = [&](int code) {
+        std::string msg = c->err;
+        free_all(c);
+        delete c;
+        g_init_error = msg;
+        return code;
+    };
+
+    // problem arrays
+    if (p->mem == ASAGA_MEM_HOST) {
+        c->nnz = p->rowptr[p->n];
+        c->own = true;
+        if ((rc = dalloc(c, &c->rowptr, c->n + 1))) return bail(rc);
+        if ((rc = dalloc(c, &c->colidx, c->nnz))) return bail(rc);
+        char* vp = nullptr;
+        if ((rc = dalloc(c, &vp, c->nnz * (int64_t)val_size(c->val_dtype)))) return bail(rc);
+        c->val = vp;
+        if ((rc = dalloc(c, &c->b, c->n))) return bail(rc);
+        const hipStream_t st = c->st;
+        if ((rc = [&]() -> int {
+                 HIPCHK(c, hipMemcpyAsync(c->rowptr, p->rowptr, (c->n + 1) * 8, hipMemcpyHostToDevice, st));
+                 HIPCHK(c, hipMemcpyAsync(c->colidx, p->colidx, c->nnz * 4, hipMemcpyHostToDevice, st));
+                 HIPCHK(c, hipMemcpyAsync(c->val, p->val, c->nnz * val_size(c->val_dtype), hipMemcpyHostToDevice, st));
+                 HIPCHK(c, hipMemcpyAsync(c->b, p->b, c->n * 8, hipMemcpyHostToDevice, st));
+                 return ASAGA_OK;
+             }()))
+            return bail(rc);
+    } else {
+        c->own = false;
+        c->rowptr = const_cast<int64_t*>(p->rowptr);
+        c->colidx = const_cast<int32_t*>(p->colidx);
+        c->val = const_cast<void*>(p->val);
+        c->b = const_cast<double*>(p->b);
+    }
+
+    // scratch
+    if ((rc = dalloc(c, &c->flag, 1))) return bail(rc);
+    if ((rc = dalloc(c, &c->stats, 2))) return bail(rc);
+    if ((rc = dalloc(c, &c->maxbits, 1))) return bail(rc);
+    if ((rc = dalloc(c, &c->part, kSumParts))) return bail(rc);
+    if ((rc = dalloc(c, &c->scal, 4))) return bail(rc);
+    if ((rc = dalloc(c, &c->z, c->n))) return bail(rc);
+    if ((rc = dalloc(c, &c->tmp, c->n))) return bail(rc);
+    if ((rc = dalloc(c, &c->vecd, c->d))) return bail(rc);
+    if ((rc = dalloc(c, &c->xin, c->d))) return bail(rc);
+    if ((rc = [&]() -> int {
+             HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->st));
+             return ASAGA_OK;
+         }()))
+        return bail(rc);
+
+    if (p->mem == ASAGA_MEM_DEVICE) {
+        // nnz from the device rowptr, then a device-side validation pass
+        int64_t ends[2];
+        if ((rc = [&]() -> int {
+                 HIPCHK(c, hipMemcpyAsync(&ends[0], c->rowptr, 8, hipMemcpyDeviceToHost, c->st));
+                 HIPCHK(c, hipMemcpyAsync(&ends[1], c->rowptr + c->n, 8, hipMemcpyDeviceToHost, c->st));
+                 HIPCHK(c, hipStreamSynchronize(c->st));
+                 return ASAGA_OK;
+             }()))
+            return bail(rc);
+        if (ends[0] != 0 || ends[1] < c->n || ends[1] > ((int64_t)1 << 40)) {
+            c->err = "rowptr[0] != 0 or rowptr[n] out of range";
+            return bail(ASAGA_E_CSR);
+        }
+        c->nnz = ends[1];
+        int32_t bad = 0;
+        if ((rc = [&]() -> int {
+                 HIPCHK(c, hipMemsetAsync(c->stats, 0, sizeof(int32_t), c->st));
+                 HIPCHK(c, launch_validate(mat(c), c->nnz, c->stats, c->st));
+                 HIPCHK(c, hipMemcpyAsync(&bad, c->stats, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+                 HIPCHK(c, hipStreamSynchronize(c->st));
+                 return ASAGA_OK;
+             }()))
+            return bail(rc);
+        if (bad) {
+            c->err = "device CSR validation failed (flags " + std::to_string(bad) +
+                     ": 1 rowptr, 2 empty row, 4 column range, 8 column order, 16 value, 32 label)";
+            return bail(ASAGA_E_CSR);
+        }
+    }
+
+    // instances
+    if (!bt) {
+        Inst I;
+        I.m = c->n;
+        I.lambda = p->lambda;
+        I.seed = o->seed;
+        c->inst.push_back(I);
+    } else {
+        std::vector<int32_t> rows;
+        for (int k = 0; k < bt->n_inst; ++k) {
+            Inst I;
+            I.lambda = bt->inst_lambda[k];
+            I.seed = o->seed + (uint64_t)k;
+            const int f = bt->inst_fold[k];
+            if (f < 0) {
+                I.m = c->n;
+            } else {
+                rows.clear();
+                for (int64_t i = 0; i < c->n; ++i)
+                    if (bt->row_fold[i] != f) rows.push_back((int32_t)i);
+                I.m = (int64_t)rows.size();
+                if (I.m == 0) {
+                    c->err = "an instance has no training rows";
+                    return bail(ASAGA_E_ARG);
+                }
+                if ((rc = dalloc(c, &I.rows, I.m))) return bail(rc);
+                if ((rc = [&]() -> int {
+                         HIPCHK(c, hipMemcpyAsync(I.rows, rows.data(), I.m * 4, hipMemcpyHostToDevice, c->st));
+                         HIPCHK(c, hipStreamSynchronize(c->st));
+                         return ASAGA_OK;
+                     }()))
+                    return bail(rc);
+            }
+            c->inst.push_back(I);
+        }
+    }
+    for (auto& I : c->inst)
+        if ((rc = setup_instance(c, I))) return bail(rc);
+    pick_shape(c);
+    if (bt) {
+        if ((rc = dalloc(c, &c->d_insts, (int64_t)c->inst.size()))) return bail(rc);
+        int wpi = c->o.waves > 0 ? c->o.waves : c->waves / (int)c->inst.size();
+        if (wpi < 1) wpi = 1;
+        c->waves_per_inst = wpi;
+    }
+    if ((rc = [&]() -> int {
+             HIPCHK(c, hipStreamSynchronize(c->st));
+             return ASAGA_OK;
+         }()))
+        return bail(rc);
+    *out = c;
+    return ASAGA_OK;
+}
+
+int check_inst(asaga_ctx* c, int32_t inst) {
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return fail(c, ASAGA_E_ARG, "instance out of range");
+    return ASAGA_OK;
+}
+
+// x of instance `inst` (or the host vector) as a device pointer for evaluation
+int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, const void** x, bool* f32) {
+    if (x_host) {
+        HIPCHK(c, hipMemcpyAsync(c->xin, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+        *x = c->xin;
+        *f32 = false;
+    } else {
+        *x = c->inst[inst].x;
+        *f32 = c->mixed;
+    }
+    return ASAGA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int asaga_init(asaga_ctx** out, const asaga_problem* prob, const asaga_opts* opts) {
+    return init_common(out, prob, opts, nullptr);
+}
+
+int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_opts* opts, const asaga_batch* batch) {
+    if (!batch) return fail(nullptr, ASAGA_E_ARG, "NULL batch descriptor");
+    return init_common(out, prob, opts, batch);
+}
+
+int asaga_updates(asaga_ctx* c, int64_t count) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (count < 0) return fail(c, ASAGA_E_ARG, "negative update count");
+    if (c->inst.size() != 1) return fail(c, ASAGA_E_STATE, "asaga_updates needs a single-instance context");
+    Inst& I = c->inst[0];
+    UpdateShape S;
+    S.serial = c->o.mode == ASAGA_MODE_SERIAL;
+    S.lanes = S.serial ? 64 : c->lanes;
+    S.waves = S.serial ? 1 : c->waves;
+    S.racy = c->o.racy != 0;
+    S.mixed = c->mixed;
+    // serial launches are cut into pieces of at most 2^18 updates
+    const int64_t piece = S.serial ? ((int64_t)1 << 18) : count;
+    for (int64_t done = 0; done < count;) {
+        const int64_t k = count - done < piece ? count - done : piece;
+        HIPCHK(c, launch_updates(mat(c), inst_args(c, I, (uint64_t)I.t, (uint64_t)k), S, c->flag, c->st));
+        I.t += k;
+        done += k;
+    }
+    return ASAGA_OK;
+}
+
+int asaga_epochs(asaga_ctx* c, int64_t n_epochs) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (n_epochs < 0) return fail(c, ASAGA_E_ARG, "negative epoch count");
+    if (c->inst.size() == 1 && !c->d_insts) {
+        for (int64_t e = 0; e < n_epochs; ++e) {
+            int rc = asaga_updates(c, c->inst[0].m);
+            if (rc) return rc;
+        }
+        return ASAGA_OK;
+    }
+    UpdateShape S;
+    S.serial = false;
+    S.lanes = c->lanes;
+    S.waves = c->waves;
+    S.racy = false;
+    S.mixed = c->mixed;
+    std::vector<InstArgs> h(c->inst.size());
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        const Inst& I = c->inst[k];
+        h[k] = inst_args(c, I, (uint64_t)I.t, (uint64_t)I.m);
+    }
+    // the previous call's launches read the descriptors: wait before overwriting them
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpyAsync(c->d_insts, h.data(), h.size() * sizeof(InstArgs), hipMemcpyHostToDevice, c->st));
+    for (int64_t e = 0; e < n_epochs; ++e)
+        HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), c->waves_per_inst, (uint64_t)e, S,
+                                         c->flag, c->st));
+    for (auto& I : c->inst) I.t += n_epochs * I.m;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return ASAGA_OK;
+}
+
+int asaga_objective(asaga_ctx* c, int32_t inst, const double* x_host, double* f_out) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!f_out) return fail(c, ASAGA_E_ARG, "NULL f_out");
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst];
+    const void* x;
+    bool f32;
+    if ((rc = eval_x(c, inst, x_host, &x, &f32))) return rc;
+    const MatArgs A = mat(c);
+    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, f32, c->z, c->st));
+    HIPCHK(c, launch_phi_terms(A, I.rows, I.m, c->z, c->tmp, c->st));
+    HIPCHK(c, launch_sum(c->tmp, I.m, false, c->part, c->scal + 0, c->st));
+    HIPCHK(c, launch_sum_x2(x, f32, c->d, c->part, c->scal + 1, c->st));
+    double s[2];
+    HIPCHK(c, hipMemcpyAsync(s, c->scal, sizeof(s), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    const double f = s[0] / (double)I.m + 0.5 * I.lambda * s[1];
+    *f_out = f;
+    if (!std::isfinite(f)) return fail(c, ASAGA_E_DIVERGED, "objective is not finite");
+    return ASAGA_OK;
+}
+
+int asaga_full_grad(asaga_ctx* c, int32_t inst, const double* x_host, double* g_host) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!g_host) return fail(c, ASAGA_E_ARG, "NULL g_host");
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst];
+    const void* x;
+    bool f32;
+    if ((rc = eval_x(c, inst, x_host, &x, &f32))) return rc;
+    const MatArgs A = mat(c);
+    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, f32, c->z, c->st));
+    HIPCHK(c, launch_dphi_coef(A, I.rows, I.m, c->z, 1.0 / (double)I.m, c->tmp, c->st));
+    HIPCHK(c, launch_fill_f64(c->vecd, 0.0, c->d, c->st));
+    HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, c->vecd, c->st));
+    HIPCHK(c, launch_axpy_x(x, f32, c->d, I.lambda, c->vecd, c->st));
+    HIPCHK(c, hipMemcpyAsync(g_host, c->vecd, c->d * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return ASAGA_OK;
+}
+
+int asaga_get_state(asaga_ctx* c, int32_t inst, double* x_host, double* alpha_host, double* abar_host, int64_t* t_out) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst];
+    if (x_host) {
+        if (c->mixed) {
+            HIPCHK(c, launch_widen_f32(static_cast<const float*>(I.x), c->d, c->vecd, c->st));
+            HIPCHK(c, hipMemcpyAsync(x_host, c->vecd, c->d * 8, hipMemcpyDeviceToHost, c->st));
+        } else {
+            HIPCHK(c, hipMemcpyAsync(x_host, I.x, c->d * 8, hipMemcpyDeviceToHost, c->st));
+        }
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    if (alpha_host) {
+        if (c->mixed) {
+            HIPCHK(c, launch_widen_f32(static_cast<const float*>(I.alpha), I.m, c->tmp, c->st));
+            HIPCHK(c, hipMemcpyAsync(alpha_host, c->tmp, I.m * 8, hipMemcpyDeviceToHost, c->st));
+        } else {
+            HIPCHK(c, hipMemcpyAsync(alpha_host, I.alpha, I.m * 8, hipMemcpyDeviceToHost, c->st));
+        }
+    }
+    if (abar_host) HIPCHK(c, hipMemcpyAsync(abar_host, I.abar, c->d * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (t_out) *t_out = I.t;
+    return check_flag(c);
+}
+
+int asaga_get_x(asaga_ctx* c, int32_t inst, double* x_host) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!x_host) return fail(c, ASAGA_E_ARG, "NULL x_host");
+    return asaga_get_state(c, inst, x_host, nullptr, nullptr, nullptr);
+}
+
+int asaga_set_state(asaga_ctx* c, int32_t inst, const double* x_host, const double* alpha_host, const double* abar_host,
+                    const int64_t* t_in) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    Inst& I = c->inst[inst];
+    if (t_in && *t_in < 0) return fail(c, ASAGA_E_ARG, "negative sample counter");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (x_host) {
+        if (c->mixed) {
+            HIPCHK(c, hipMemcpyAsync(c->vecd, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+            HIPCHK(c, launch_narrow_f64(c->vecd, c->d, static_cast<float*>(I.x), c->st));
+        } else {
+            HIPCHK(c, hipMemcpyAsync(I.x, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+        }
+    }
+    if (alpha_host) {
+        if (c->mixed) {
+            HIPCHK(c, hipMemcpyAsync(c->tmp, alpha_host, I.m * 8, hipMemcpyHostToDevice, c->st));
+            HIPCHK(c, launch_narrow_f64(c->tmp, I.m, static_cast<float*>(I.alpha), c->st));
+        } else {
+            HIPCHK(c, hipMemcpyAsync(I.alpha, alpha_host, I.m * 8, hipMemcpyHostToDevice, c->st));
+        }
+    }
+    if (abar_host) HIPCHK(c, hipMemcpyAsync(I.abar, abar_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (t_in) I.t = *t_in;
+    return ASAGA_OK;
+}
+
+int asaga_reanchor(asaga_ctx* c) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    const MatArgs A = mat(c);
+    for (auto& I : c->inst) {
+        HIPCHK(c, launch_alpha_coef(I.alpha, c->mixed, I.m, 1.0 / (double)I.m, c->tmp, c->st));
+        HIPCHK(c, launch_fill_f64(I.abar, 0.0, c->d, c->st));
+        HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.abar, c->st));
+    }
+    return ASAGA_OK;
+}
+
+int asaga_info_get(asaga_ctx* c, asaga_info* out) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!out) return fail(c, ASAGA_E_ARG, "NULL info");
+    const Inst& I = c->inst[0];
+    out->n = c->n;
+    out->d = c->d;
+    out->nnz = c->nnz;
+    out->delta_r = I.delta_r;
+    out->t = I.t;
+    out->L = I.L;
+    out->gamma = I.gamma;
+    out->lambda = I.lambda;
+    out->waves = c->o.mode == ASAGA_MODE_SERIAL ? 1 : (c->d_insts ? c->waves_per_inst * (int)c->inst.size() : c->waves);
+    out->lanes_per_sample = c->o.mode == ASAGA_MODE_SERIAL ? 64 : c->lanes;
+    out->n_inst = (int32_t)c->inst.size();
+    out->reserved = 0;
+    return ASAGA_OK;
+}
+
+int asaga_sync(asaga_ctx* c) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return check_flag(c);
+}
+
+int asaga_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, int64_t* out_host) {
+    if (count < 0 || n < 1 || (!out_host && count > 0)) return fail(nullptr, ASAGA_E_ARG, "bad sample stream arguments");
+    if (count == 0) return ASAGA_OK;
+    int64_t* d = nullptr;
+    hipError_t e = hipMalloc(&d, (size_t)count * 8);
+    if (e != hipSuccess) return fail(nullptr, ASAGA_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    e = launch_sample_stream(seed, t0, count, n, d, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out_host, d, (size_t)count * 8, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(nullptr, ASAGA_E_HIP, std::string("sample stream: ") + hipGetErrorString(e));
+    return ASAGA_OK;
+}
+
+const char* asaga_last_error(const asaga_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+void asaga_free(asaga_ctx* c) {
+    if (!c) return;
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

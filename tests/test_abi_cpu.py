@@ -1,0 +1,107 @@
+"""The C ABI without a GPU: the library loads, exports every function that
+include/asaga.h declares, and rejects malformed problems on the host before
+touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+A = pytest.importorskip("paper_1606_04809_amd")
+
+HEADER = os.path.join(ROOT, "include", "asaga.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(asaga_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    lib = ctypes.CDLL(A.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(A.EXPORTED) == names
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and field offsets as the C compiler lays out asaga.h
+    src = tmp_path / "layout.c"
+    checks = []
+    for cname, py in (("asaga_problem", A.asaga_problem), ("asaga_opts", A.asaga_opts),
+                      ("asaga_batch", A.asaga_batch), ("asaga_info", A.asaga_info)):
+        checks.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = {"lam": "lambda"}.get(fname, fname)
+            checks.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {cf}));')
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"asaga.h\"\nint main(void){"
+                   + "".join(checks) + "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in (("asaga_problem", A.asaga_problem), ("asaga_opts", A.asaga_opts),
+                      ("asaga_batch", A.asaga_batch), ("asaga_info", A.asaga_info)):
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
+
+
+def good():
+    return dict(n=3, d=4, rowptr=np.array([0, 2, 3, 5]), colidx=np.array([0, 2, 1, 0, 3], np.int32),
+                val=np.array([1.0, -0.5, 2.0, 0.3, 0.7]), b=np.array([1.0, -1.0, 1.0]), lam=0.1)
+
+
+def expect(code, **changes):
+    kw = good()
+    opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
+                                                              "waves", "step", "loss")}
+    kw.update(changes)
+    with pytest.raises(A.AsagaError) as ei:
+        A.Solver(**kw, **opts)
+    assert ei.value.code == code, str(ei.value)
+    assert A.asaga_last_error(None)
+
+
+def test_malformed_csr_is_rejected_on_host():
+    E = A.ASAGA_E_CSR
+    expect(E, rowptr=np.array([1, 2, 3, 5]))                      # rowptr[0] != 0
+    expect(E, rowptr=np.array([0, 3, 2, 5]))                      # decreasing
+    expect(E, rowptr=np.array([0, 2, 2, 5]))                      # empty row
+    expect(E, colidx=np.array([0, 2, 1, 0, 4], np.int32))        # column out of range
+    expect(E, colidx=np.array([0, 2, 1, 0, -1], np.int32))       # negative column
+    expect(E, colidx=np.array([2, 0, 1, 0, 3], np.int32))        # not increasing
+    expect(E, colidx=np.array([0, 0, 1, 0, 3], np.int32))        # duplicate
+    expect(E, val=np.array([1.0, np.nan, 2.0, 0.3, 0.7]))        # non-finite value
+    expect(E, val=np.array([1.0, np.inf, 2.0, 0.3, 0.7]))
+    expect(E, b=np.array([1.0, 0.0, 1.0]))                       # logistic label not +-1
+    expect(E, b=np.array([1.0, np.nan, 1.0]), loss=A.ASAGA_LOSS_SQUARED)
+
+
+def test_bad_arguments_are_rejected():
+    E = A.ASAGA_E_ARG
+    expect(E, lam=0.0)
+    expect(E, lam=-1.0)
+    expect(E, lam=float("inf"))
+    expect(E, mode=7)
+    expect(E, precision=3)
+    expect(E, lanes_per_sample=12)
+    expect(E, racy=1)                                            # racy needs async mode
+    expect(E, waves=-1)
+    expect(E, step=float("nan"))
+    expect(E, loss=5)
+    expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = ctypes.CDLL(A.LIB_PATH)
+    lib.asaga_epochs.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    assert lib.asaga_epochs(None, 1) == A.ASAGA_E_ARG
+    lib.asaga_free.argtypes = [ctypes.c_void_p]
+    lib.asaga_free(None)

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from conftest import rel_err
+
+pytestmark = pytest.mark.gpu
+
+A = pytest.importorskip("paper_1606_04809_amd")
+
+
+def say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def ragged_problem(seed=0, n=300, d=700, loss=datagen.LOGISTIC, lam=None):
+    """Rows of very uneven length: 1 .. 400 entries (several rows longer than
+    the 128 entries kept in registers), columns uniform."""
+    rng = np.random.default_rng(seed)
+    k = np.concatenate([[1, 2, 129, 400, 257, 64, 65, 128], rng.integers(1, 90, size=n - 8)])
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(k, out=rowptr[1:])
+    cols = [np.sort(rng.choice(d, size=int(kk), replace=False)) for kk in k]
+    colidx = np.concatenate(cols).astype(np.int32)
+    val = rng.standard_normal(len(colidx))
+    val /= np.repeat(np.sqrt(np.add.reduceat(val * val, rowptr[:-1])), k)
+    b = np.where(rng.random(n) < 0.5, 1.0, -1.0) if loss == datagen.LOGISTIC else rng.standard_normal(n)
+    return datagen.Problem("ragged", n, d, rowptr, colidx, val, b, loss, lam if lam else 1.0 / n)
+
+
+def compare_serial(p, epochs, seed=0, tol=1e-12, per_epoch=True, **kw):
+    sv = oracle.SparseSaga(p, seed=seed)
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, seed=seed, **kw) as g:
+        info = g.info()
+        assert info.gamma == pytest.approx(sv.gamma, rel=1e-14)
+        assert info.delta_r == sv.cnt.max()
+        worst = 0.0
+        for e in range(epochs):
+            g.epochs(1)
+            sv.epochs(1)
+            if per_epoch or e == epochs - 1:
+                x, alpha, abar, t = g.get_state()
+                assert t == sv.state.t
+                errs = (rel_err(x, sv.state.x), rel_err(alpha, sv.state.alpha), rel_err(abar, sv.state.abar))
+                worst = max(worst, *errs)
+                assert max(errs) <= tol, (e, errs)
+        return worst
+
+
+def test_single_hip_runtime_in_process():
+    A.asaga_sample_stream(0, 0, 16, 10)
+    assert len(A.hip_runtimes_loaded()) == 1, A.hip_runtimes_loaded()
+
+
+def test_sample_stream_matches_oracle():
+    for seed, t0, n in ((0, 0, 700_000), (12345, 10**12, 2_400_000), (7, 3, 1)):
+        gpu = A.asaga_sample_stream(seed, t0, 1_000_000, n)
+        assert np.array_equal(gpu, oracle.sample_stream(seed, t0, 1_000_000, n))
+
+
+def test_serial_parity_config1(golden):
+    p = datagen.config1()
+    worst = compare_serial(p, 50)
+    say(f"config1 serial: worst rel err over 50 epochs {worst:.2e}")
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL) as g:
+        g.epochs(50)
+        f = g.objective()
+    assert (f - golden["config1"]["f_star"]) / golden["config1"]["f_star"] <= 1e-12
+
+
+def test_serial_parity_ragged_rows_both_losses():
+    for loss in (datagen.LOGISTIC, datagen.SQUARED):
+        compare_serial(ragged_problem(loss=loss), 6)
+
+
+def test_serial_parity_config3_subset():
+    compare_serial(datagen.config3(n=5000), 8)
+
+
+def test_serial_parity_config2_scaled():
+    compare_serial(datagen.config2(n=7000, d=4700), 5)
+
+
+@pytest.mark.slow
+def test_serial_parity_config2_full_one_epoch():
+    p = datagen.config2()
+    compare_serial(p, 1)
+
+
+def test_degenerate_shapes():
+    # n = 1, d = 1, a row with every column, empty columns (D = 0, x stays 0)
+    one = datagen.Problem("n1", 1, 5, np.array([0, 3]), np.array([0, 2, 4], np.int32), np.array([0.5, -1.0, 2.0]),
+                          np.array([1.0]), datagen.LOGISTIC, 0.3)
+    compare_serial(one, 40)
+    d1 = datagen.Problem("d1", 4, 1, np.arange(5), np.zeros(4, np.int32), np.array([1.0, -2.0, 0.5, 3.0]),
+                         np.array([1.0, -1.0, 1.0, 1.0]), datagen.LOGISTIC, 0.01)
+    compare_serial(d1, 30)
+    p = ragged_problem(n=50, d=2000)
+    cnt = np.bincount(p.colidx, minlength=p.d)
+    assert (cnt == 0).any()
+    compare_serial(p, 4)
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL) as g:
+        g.epochs(3)
+        assert np.all(g.get_x()[cnt == 0] == 0.0)
+
+
+def test_objective_and_gradient_match_oracle():
+    rng = np.random.default_rng(0)
+    for p in (datagen.config1(), datagen.config3(n=20_000), ragged_problem(), datagen.config2(n=7000, d=4700)):
+        sv = oracle.SparseSaga(p)
+        x = rng.standard_normal(p.d) * 0.1
+        with A.from_problem(p) as g:
+            f = g.objective(x=x)
+            gr = g.full_grad(x=x)
+            assert f == pytest.approx(sv.objective(x), rel=1e-13)
+            assert rel_err(gr, sv.gradient(x)) < 1e-13
+            # the current iterate (zero) path
+            assert g.objective() == pytest.approx(sv.objective(np.zeros(p.d)), rel=1e-14)
+
+
+def test_resume_from_saved_state_is_identical():
+    p = datagen.config2(n=5000, d=3000)
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, seed=3) as g:
+        g.epochs(2)
+        saved = g.get_state()
+        g.epochs(2)
+        ref = g.get_state()
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, seed=3) as h:
+        x, alpha, abar, t = saved
+        h.set_state(x=x, alpha=alpha, abar=abar, t=t)
+        h.epochs(2)
+        got = h.get_state()
+    for a, b in zip(got[:3], ref[:3]):
+        assert np.array_equal(a, b)
+    assert got[3] == ref[3] == 4 * p.n
+
+
+def test_device_memory_inputs_match_host_inputs():
+    torch = pytest.importorskip("torch")
+    p = datagen.config2(n=6000, d=4000)
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (p.rowptr, p.colidx, p.val, p.b)]
+    stream = torch.cuda.current_stream()
+    with A.Solver(p.n, p.d, *dev, p.lam, mode=A.ASAGA_MODE_SERIAL, stream=stream) as g, \
+            A.from_problem(p, mode=A.ASAGA_MODE_SERIAL) as h:
+        g.epochs(2)
+        h.epochs(2)
+        assert np.array_equal(g.get_x(), h.get_x())
+
+
+def test_device_validation_rejects_malformed_csr():
+    torch = pytest.importorskip("torch")
+    p = datagen.config1(n=50, d=20, k=4)
+    bad_cols = p.colidx.copy()
+    bad_cols[5] = 25                                       # out of range
+    bad_lab = p.b.copy()
+    bad_lab[3] = 0.5                                       # not +-1 for the logistic loss
+    for rp, ci, b in ((p.rowptr, bad_cols, p.b), (p.rowptr, p.colidx, bad_lab)):
+        dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (rp, ci, p.val, b)]
+        with pytest.raises(A.AsagaError) as ei:
+            A.Solver(p.n, p.d, *dev, p.lam)
+        assert ei.value.code == A.ASAGA_E_CSR
+
+
+def test_async_small_reaches_optimum():
+    p = datagen.config2(n=20_000, d=5000)
+    r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
+    assert r["converged"]
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=256) as g:
+        for e in range(200):
+            g.epochs(5)
+            f = g.objective()
+            if (f - r["f_lower"]) / r["f_lower"] <= 1e-10:
+                break
+        say(f"async small: {5 * (e + 1)} epochs, rel subopt {(f - r['f_lower']) / r['f_lower']:.2e}")
+        assert (f - r["f_lower"]) / r["f_lower"] <= 1e-10
+        # abar stays the running average of the memory up to rounding
+        x, alpha, abar, t = g.get_state()
+        sv = oracle.SparseSaga(p)
+        assert rel_err(abar, sv.memory_average(alpha)) < 1e-11
+
+
+@pytest.mark.slow
+def test_async_config2_full_reaches_1e9(golden):
+    p = datagen.config2()
+    assert p.digest() == golden["config2"]["digest"]
+    fstar = golden["config2"]["f_lower"]
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC) as g:
+        info = g.info()
+        say(f"config2 async: waves {info.waves} lanes {info.lanes_per_sample} gamma {info.gamma}")
+        hist = []
+        for e in range(60):
+            g.epochs(1)
+            rel = (g.objective() - fstar) / fstar
+            hist.append(rel)
+            if rel <= 1e-9:
+                break
+        say(f"config2 async: epochs {len(hist)} rel {hist[-1]:.3e}")
+        assert hist[-1] <= 1e-9
