@@ -36,6 +36,13 @@
  *
  * Step size: when opts.step <= 0, gamma = min(1/(3L), 1/(lambda max_v D_v))
  * with L = c max_i ||a_i||^2 + lambda, c = 1/4 (logistic) or 1 (squared).
+ * With many samples in flight, updates read state that is older by up to
+ * tau samples (Section 3.3, Assumption 1); the step must then shrink like
+ * 1/tau along the directions many rows share (Theorem 2).  Async callers
+ * pass a step chosen for their launch shape (see the autotuning notes).
+ *
+ * Columns are relabelled internally by descending count; every vector that
+ * crosses this interface (x, gradients, abar) is in the caller's order.
  *
  * Conventions:
  *   - Every function returns ASAGA_OK (0) or a negative ASAGA_E_* code; the
@@ -94,8 +101,8 @@ typedef struct asaga_ctx asaga_ctx;
 /* The data of the problem.  CSR requirements (checked by asaga_init):
  * rowptr[0] = 0, rowptr nondecreasing, every row non-empty, rowptr[n] = nnz,
  * 0 <= colidx < d and strictly increasing within each row, values finite,
- * b finite and, for the logistic loss, in {-1, +1}; n >= 1, d >= 1,
- * lambda > 0 and finite.  Layout: rowptr int64[n+1], colidx int32[nnz],
+ * b finite and, for the logistic loss, in {-1, +1}; 1 <= n < 2^31,
+ * 1 <= d < 2^27, lambda > 0 and finite.  Layout: rowptr int64[n+1], colidx int32[nnz],
  * val[nnz] of type val_dtype, b double[n]. */
 typedef struct asaga_problem {
     int64_t n;
@@ -124,7 +131,14 @@ typedef struct asaga_opts {
     int32_t racy;             /* 1: plain read-modify-write instead of atomic adds
                                  (the non-thread-safe variant of App. G; a
                                  negative control, async only)                    */
-    int32_t reserved[3];      /* must be 0 */
+    int32_t hot_columns;      /* async: the H most-used columns whose writes each
+                                 workgroup combines in LDS before adding them to
+                                 the shared state (0 = automatic, -1 = none;
+                                 at most 4096)                                    */
+    int32_t flush_every;      /* async: samples each lane group applies between
+                                 two flushes of those combined writes
+                                 (0 = automatic)                                  */
+    int32_t reserved;         /* must be 0 */
     void* stream;             /* hipStream_t */
 } asaga_opts;
 
@@ -151,9 +165,11 @@ typedef struct asaga_info {
     double L;          /* smoothness constant used by the step-size rule            */
     double gamma;      /* step size in use (instance 0)                             */
     double lambda;     /* instance 0                                                */
-    int32_t waves;     /* async launch: wavefronts in flight                        */
+    int32_t waves;     /* async launch: wavefronts in flight (per instance if batched) */
     int32_t lanes_per_sample;
     int32_t n_inst;
+    int32_t hot_columns;
+    int32_t flush_every;
     int32_t reserved;
 } asaga_info;
 

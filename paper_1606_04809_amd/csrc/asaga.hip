@@ -1,10 +1,13 @@
 // C ABI of the gfx950 Sparse SAGA / ASAGA library (declared in asaga.h):
-// validation, device memory, the step-size rule, launches, read-back.
+// validation, column relabelling, device memory, the step-size rule,
+// launches, read-back in the caller's column order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -17,17 +20,19 @@ namespace {
 
 thread_local std::string g_init_error = "no error";
 
+constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
+constexpr int kMaxHot = 4096;  // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
+
 struct Inst {
     int64_t m = 0;
     int32_t* rows = nullptr;  // device, nullptr = identity
     double lambda = 0.0, gamma = 0.0, L = 0.0;
     int64_t delta_r = 0;
     int32_t cnt_min = 0;
-    int32_t* cnt = nullptr;
-    double* D = nullptr;
-    void* x = nullptr;
-    void* alpha = nullptr;
-    double* abar = nullptr;
+    int32_t* cnt = nullptr;   // relabelled order
+    double* D = nullptr;      // relabelled order
+    double* xa = nullptr;     // [2d] interleaved x / abar, relabelled order
+    void* alpha = nullptr;    // [m]
     uint64_t seed = 0;
     int64_t t = 0;
 };
@@ -37,23 +42,24 @@ struct Inst {
 struct asaga_ctx {
     int64_t n = 0, d = 0, nnz = 0;
     int32_t loss = 0, val_dtype = 0;
-    bool own = false;
     int64_t* rowptr = nullptr;
-    int32_t* colidx = nullptr;
+    const int32_t* colidx_in = nullptr;  // caller's column indices (device)
+    int32_t* colidx = nullptr;           // relabelled copy (device, owned)
+    int32_t* rank = nullptr;             // [d] caller's column -> internal column
     void* val = nullptr;
     double* b = nullptr;
     asaga_opts o{};
     hipStream_t st = nullptr;
     bool mixed = false;
-    int lanes = 64, waves = 1, waves_per_inst = 0;
+    UpdateShape shape{};
     std::vector<Inst> inst;
     InstArgs* d_insts = nullptr;
     std::vector<void*> allocs;
     // scratch
     double* z = nullptr;      // [n]
     double* tmp = nullptr;    // [n]
-    double* vecd = nullptr;   // [d]
-    double* xin = nullptr;    // [d]
+    double* vec1 = nullptr;   // [d]
+    double* vec2 = nullptr;   // [d]
     double* part = nullptr;   // [kSumParts]
     double* scal = nullptr;   // [4]
     int* flag = nullptr;      // [1]
@@ -135,8 +141,9 @@ int validate_host(const asaga_problem* p) {
 
 int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (!p || !o) return fail(nullptr, ASAGA_E_ARG, "NULL problem or options");
-    if (p->n < 1 || p->d < 1 || p->d > INT32_MAX || p->n > INT32_MAX)
-        return fail(nullptr, ASAGA_E_ARG, "n and d must be in [1, 2^31)");
+    if (p->n < 1 || p->d < 1 || p->n > INT32_MAX)
+        return fail(nullptr, ASAGA_E_ARG, "n must be in [1, 2^31) and d >= 1");
+    if (p->d > kMaxD) return fail(nullptr, ASAGA_E_ARG, "d must be at most 2^27 - 1 (16-byte state slots, 32-bit offsets)");
     if (!p->rowptr || !p->colidx || !p->val || !p->b) return fail(nullptr, ASAGA_E_ARG, "NULL problem array");
     if (p->val_dtype < ASAGA_VAL_F64 || p->val_dtype > ASAGA_VAL_BF16)
         return fail(nullptr, ASAGA_E_ARG, "bad val_dtype");
@@ -154,15 +161,17 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
         return fail(nullptr, ASAGA_E_ARG, "lanes_per_sample must be 0, 8, 16, 32 or 64");
     if (o->racy != 0 && o->racy != 1) return fail(nullptr, ASAGA_E_ARG, "racy must be 0 or 1");
     if (o->racy && o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "racy applies to async mode only");
-    for (int r = 0; r < 3; ++r)
-        if (o->reserved[r] != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
+    if (o->hot_columns < -1 || o->hot_columns > kMaxHot)
+        return fail(nullptr, ASAGA_E_ARG, "hot_columns must be -1, 0 or in [1, 4096]");
+    if (o->flush_every < 0 || o->flush_every > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "flush_every out of range");
+    if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
     return ASAGA_OK;
 }
 
-MatArgs mat(const asaga_ctx* c) {
+MatArgs mat(const asaga_ctx* c, bool relabelled = true) {
     MatArgs A;
     A.rowptr = c->rowptr;
-    A.colidx = c->colidx;
+    A.colidx = relabelled ? c->colidx : c->colidx_in;
     A.val = c->val;
     A.b = c->b;
     A.n = c->n;
@@ -172,12 +181,11 @@ MatArgs mat(const asaga_ctx* c) {
     return A;
 }
 
-InstArgs inst_args(const asaga_ctx* c, const Inst& I, uint64_t t0, uint64_t count) {
+InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
     InstArgs a;
     a.rows = I.rows;
-    a.x = I.x;
+    a.xa = I.xa;
     a.alpha = I.alpha;
-    a.abar = I.abar;
     a.D = I.D;
     a.m = I.m;
     a.gamma = I.gamma;
@@ -186,48 +194,63 @@ InstArgs inst_args(const asaga_ctx* c, const Inst& I, uint64_t t0, uint64_t coun
     a.seed = I.seed;
     a.t0 = t0;
     a.count = count;
-    (void)c;
     return a;
 }
 
+// views of an instance's state in the relabelled order
+XView x_view(const asaga_ctx* c, const Inst& I) { return c->mixed ? XView{I.xa, 4, 1} : XView{I.xa, 2, 0}; }
+XView abar_view(const Inst& I) { return XView{I.xa + 1, 2, 0}; }
+
 int zero_state(asaga_ctx* c, Inst& I) {
-    if (c->mixed) {
-        HIPCHK(c, launch_fill_f32(static_cast<float*>(I.x), 0.0f, c->d, c->st));
-        HIPCHK(c, launch_fill_f32(static_cast<float*>(I.alpha), 0.0f, I.m, c->st));
-    } else {
-        HIPCHK(c, launch_fill_f64(static_cast<double*>(I.x), 0.0, c->d, c->st));
-        HIPCHK(c, launch_fill_f64(static_cast<double*>(I.alpha), 0.0, I.m, c->st));
-    }
-    HIPCHK(c, launch_fill_f64(I.abar, 0.0, c->d, c->st));
+    HIPCHK(c, launch_fill_f64(I.xa, 0.0, 2 * c->d, 1, c->st));
+    if (c->mixed) HIPCHK(c, launch_fill_f32(static_cast<float*>(I.alpha), 0.0f, I.m, c->st));
+    else HIPCHK(c, launch_fill_f64(static_cast<double*>(I.alpha), 0.0, I.m, 1, c->st));
     I.t = 0;
+    return ASAGA_OK;
+}
+
+// Relabel columns by descending count over all rows (ties: lower index first).
+int relabel_columns(asaga_ctx* c) {
+    int rc;
+    int32_t* cnt = nullptr;
+    if ((rc = dalloc(c, &cnt, c->d))) return rc;
+    if ((rc = dalloc(c, &c->rank, c->d))) return rc;
+    if ((rc = dalloc(c, &c->colidx, c->nnz))) return rc;
+    HIPCHK(c, launch_fill_i32(cnt, 0, c->d, c->st));
+    HIPCHK(c, launch_colcount(mat(c, false), nullptr, c->n, cnt, c->st));
+    std::vector<int32_t> h(c->d);
+    HIPCHK(c, hipMemcpyAsync(h.data(), cnt, c->d * 4, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::vector<int32_t> order(c->d);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return h[a] > h[b]; });
+    std::vector<int32_t> rank(c->d);
+    for (int64_t r = 0; r < c->d; ++r) rank[order[r]] = (int32_t)r;
+    HIPCHK(c, hipMemcpyAsync(c->rank, rank.data(), c->d * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, launch_relabel(c->colidx_in, c->nnz, c->rank, c->colidx, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
     return ASAGA_OK;
 }
 
 // Column counts, D, Delta_r, L and gamma of one instance; zero its state.
 int setup_instance(asaga_ctx* c, Inst& I) {
     int rc;
-    const size_t xs = c->mixed ? 4 : 8;
     if ((rc = dalloc(c, &I.cnt, c->d))) return rc;
     if ((rc = dalloc(c, &I.D, c->d))) return rc;
-    if ((rc = dalloc(c, &I.abar, c->d))) return rc;
-    char* xp = nullptr;
-    if ((rc = dalloc(c, &xp, c->d * (int64_t)xs))) return rc;
-    I.x = xp;
+    if ((rc = dalloc(c, &I.xa, 2 * c->d))) return rc;
     char* ap = nullptr;
-    if ((rc = dalloc(c, &ap, I.m * (int64_t)xs))) return rc;
+    if ((rc = dalloc(c, &ap, I.m * (int64_t)(c->mixed ? 4 : 8)))) return rc;
     I.alpha = ap;
 
     const MatArgs A = mat(c);
     HIPCHK(c, launch_fill_i32(I.cnt, 0, c->d, c->st));
     HIPCHK(c, launch_colcount(A, I.rows, I.m, I.cnt, c->st));
-    const int32_t init_stats[2] = {0, 0x7fffffff};
-    HIPCHK(c, hipMemcpyAsync(c->stats, init_stats, sizeof(init_stats), hipMemcpyHostToDevice, c->st));
+    int32_t stats[2] = {0, 0x7fffffff};
+    HIPCHK(c, hipMemcpyAsync(c->stats, stats, sizeof(stats), hipMemcpyHostToDevice, c->st));
     HIPCHK(c, launch_reweight(I.cnt, c->d, I.m, I.D, c->stats, c->st));
-    const unsigned long long zero = 0;
-    HIPCHK(c, hipMemcpyAsync(c->maxbits, &zero, sizeof(zero), hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, launch_rownorm_max(A, I.rows, I.m, c->maxbits, c->st));
-    int32_t stats[2];
     unsigned long long bits = 0;
+    HIPCHK(c, hipMemcpyAsync(c->maxbits, &bits, sizeof(bits), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, launch_rownorm_max(A, I.rows, I.m, c->maxbits, c->st));
     HIPCHK(c, hipMemcpyAsync(stats, c->stats, sizeof(stats), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipMemcpyAsync(&bits, c->maxbits, sizeof(bits), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -249,24 +272,41 @@ int setup_instance(asaga_ctx* c, Inst& I) {
 }
 
 void pick_shape(asaga_ctx* c) {
+    UpdateShape& S = c->shape;
+    S.serial = c->o.mode == ASAGA_MODE_SERIAL;
+    S.racy = c->o.racy != 0;
+    S.mixed = c->mixed;
+    if (S.serial) {
+        S.lanes = 64;
+        S.waves = 1;
+        S.block = 64;
+        S.hot = 0;
+        S.flush = 1;
+        return;
+    }
     const double mean = (double)c->nnz / (double)c->n;
     int lanes = c->o.lanes_per_sample;
     if (lanes == 0) {
-        // half the largest power of two not above the mean row length, in [8, 64]
-        int p = 1;
-        while (p * 2 <= mean && p < 128) p *= 2;
-        lanes = p / 2;
-        if (lanes < 8) lanes = 8;
-        if (lanes > 64) lanes = 64;
+        // about one lane pair per row entry, within [8, 64] lanes
+        int p = 8;
+        while (p < 64 && p < mean) p *= 2;
+        lanes = p;
     }
-    c->lanes = lanes;
+    S.lanes = lanes;
+    S.block = 512;
     int waves = c->o.waves;
     if (waves == 0) {
         int cus = device_cu_count();
         if (cus <= 0) cus = 256;
         waves = cus * 16;
     }
-    c->waves = waves;
+    const int wpb = S.block / 64;
+    S.waves = ((waves + wpb - 1) / wpb) * wpb;
+    int hot = c->o.hot_columns;
+    if (hot == 0) hot = 2048;
+    if (hot < 0 || S.racy) hot = 0;
+    S.hot = (int)std::min<int64_t>(hot, c->d);
+    S.flush = c->o.flush_every > 0 ? c->o.flush_every : 4;
 }
 
 int free_all(asaga_ctx* c) {
@@ -324,30 +364,31 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
         g_init_error = msg;
         return code;
     };
+    auto step = [&](auto&& fn) -> int { return fn(); };
 
     // problem arrays
     if (p->mem == ASAGA_MEM_HOST) {
         c->nnz = p->rowptr[p->n];
-        c->own = true;
+        int32_t* ci = nullptr;
         if ((rc = dalloc(c, &c->rowptr, c->n + 1))) return bail(rc);
-        if ((rc = dalloc(c, &c->colidx, c->nnz))) return bail(rc);
+        if ((rc = dalloc(c, &ci, c->nnz))) return bail(rc);
+        c->colidx_in = ci;
         char* vp = nullptr;
         if ((rc = dalloc(c, &vp, c->nnz * (int64_t)val_size(c->val_dtype)))) return bail(rc);
         c->val = vp;
         if ((rc = dalloc(c, &c->b, c->n))) return bail(rc);
-        const hipStream_t st = c->st;
-        if ((rc = [&]() -> int {
-                 HIPCHK(c, hipMemcpyAsync(c->rowptr, p->rowptr, (c->n + 1) * 8, hipMemcpyHostToDevice, st));
-                 HIPCHK(c, hipMemcpyAsync(c->colidx, p->colidx, c->nnz * 4, hipMemcpyHostToDevice, st));
-                 HIPCHK(c, hipMemcpyAsync(c->val, p->val, c->nnz * val_size(c->val_dtype), hipMemcpyHostToDevice, st));
-                 HIPCHK(c, hipMemcpyAsync(c->b, p->b, c->n * 8, hipMemcpyHostToDevice, st));
+        if ((rc = step([&]() -> int {
+                 HIPCHK(c, hipMemcpyAsync(c->rowptr, p->rowptr, (c->n + 1) * 8, hipMemcpyHostToDevice, c->st));
+                 HIPCHK(c, hipMemcpyAsync(ci, p->colidx, c->nnz * 4, hipMemcpyHostToDevice, c->st));
+                 HIPCHK(c, hipMemcpyAsync(c->val, p->val, c->nnz * val_size(c->val_dtype), hipMemcpyHostToDevice, c->st));
+                 HIPCHK(c, hipMemcpyAsync(c->b, p->b, c->n * 8, hipMemcpyHostToDevice, c->st));
+                 HIPCHK(c, hipStreamSynchronize(c->st));
                  return ASAGA_OK;
-             }()))
+             })))
             return bail(rc);
     } else {
-        c->own = false;
         c->rowptr = const_cast<int64_t*>(p->rowptr);
-        c->colidx = const_cast<int32_t*>(p->colidx);
+        c->colidx_in = p->colidx;
         c->val = const_cast<void*>(p->val);
         c->b = const_cast<double*>(p->b);
     }
@@ -360,23 +401,23 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
     if ((rc = dalloc(c, &c->scal, 4))) return bail(rc);
     if ((rc = dalloc(c, &c->z, c->n))) return bail(rc);
     if ((rc = dalloc(c, &c->tmp, c->n))) return bail(rc);
-    if ((rc = dalloc(c, &c->vecd, c->d))) return bail(rc);
-    if ((rc = dalloc(c, &c->xin, c->d))) return bail(rc);
-    if ((rc = [&]() -> int {
-             HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->st));
+    if ((rc = dalloc(c, &c->vec1, c->d))) return bail(rc);
+    if ((rc = dalloc(c, &c->vec2, c->d))) return bail(rc);
+    if ((rc = step([&]() -> int {
+             HIPCHK(c, launch_fill_i32(c->flag, 0, 1, c->st));
              return ASAGA_OK;
-         }()))
+         })))
         return bail(rc);
 
     if (p->mem == ASAGA_MEM_DEVICE) {
         // nnz from the device rowptr, then a device-side validation pass
         int64_t ends[2];
-        if ((rc = [&]() -> int {
+        if ((rc = step([&]() -> int {
                  HIPCHK(c, hipMemcpyAsync(&ends[0], c->rowptr, 8, hipMemcpyDeviceToHost, c->st));
                  HIPCHK(c, hipMemcpyAsync(&ends[1], c->rowptr + c->n, 8, hipMemcpyDeviceToHost, c->st));
                  HIPCHK(c, hipStreamSynchronize(c->st));
                  return ASAGA_OK;
-             }()))
+             })))
             return bail(rc);
         if (ends[0] != 0 || ends[1] < c->n || ends[1] > ((int64_t)1 << 40)) {
             c->err = "rowptr[0] != 0 or rowptr[n] out of range";
@@ -384,13 +425,13 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
         }
         c->nnz = ends[1];
         int32_t bad = 0;
-        if ((rc = [&]() -> int {
-                 HIPCHK(c, hipMemsetAsync(c->stats, 0, sizeof(int32_t), c->st));
-                 HIPCHK(c, launch_validate(mat(c), c->nnz, c->stats, c->st));
+        if ((rc = step([&]() -> int {
+                 HIPCHK(c, launch_fill_i32(c->stats, 0, 1, c->st));
+                 HIPCHK(c, launch_validate(mat(c, false), c->nnz, c->stats, c->st));
                  HIPCHK(c, hipMemcpyAsync(&bad, c->stats, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
                  HIPCHK(c, hipStreamSynchronize(c->st));
                  return ASAGA_OK;
-             }()))
+             })))
             return bail(rc);
         if (bad) {
             c->err = "device CSR validation failed (flags " + std::to_string(bad) +
@@ -398,6 +439,8 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
             return bail(ASAGA_E_CSR);
         }
     }
+
+    if ((rc = relabel_columns(c))) return bail(rc);
 
     // instances
     if (!bt) {
@@ -425,29 +468,24 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
                     return bail(ASAGA_E_ARG);
                 }
                 if ((rc = dalloc(c, &I.rows, I.m))) return bail(rc);
-                if ((rc = [&]() -> int {
+                if ((rc = step([&]() -> int {
                          HIPCHK(c, hipMemcpyAsync(I.rows, rows.data(), I.m * 4, hipMemcpyHostToDevice, c->st));
                          HIPCHK(c, hipStreamSynchronize(c->st));
                          return ASAGA_OK;
-                     }()))
+                     })))
                     return bail(rc);
             }
             c->inst.push_back(I);
         }
+        if ((rc = dalloc(c, &c->d_insts, (int64_t)c->inst.size()))) return bail(rc);
     }
     for (auto& I : c->inst)
         if ((rc = setup_instance(c, I))) return bail(rc);
     pick_shape(c);
-    if (bt) {
-        if ((rc = dalloc(c, &c->d_insts, (int64_t)c->inst.size()))) return bail(rc);
-        int wpi = c->o.waves > 0 ? c->o.waves : c->waves / (int)c->inst.size();
-        if (wpi < 1) wpi = 1;
-        c->waves_per_inst = wpi;
-    }
-    if ((rc = [&]() -> int {
+    if ((rc = step([&]() -> int {
              HIPCHK(c, hipStreamSynchronize(c->st));
              return ASAGA_OK;
-         }()))
+         })))
         return bail(rc);
     *out = c;
     return ASAGA_OK;
@@ -458,15 +496,15 @@ int check_inst(asaga_ctx* c, int32_t inst) {
     return ASAGA_OK;
 }
 
-// x of instance `inst` (or the host vector) as a device pointer for evaluation
-int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, const void** x, bool* f32) {
+// x of instance `inst`, or the caller's vector moved into the relabelled
+// order, as a view for evaluation
+int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, XView* x) {
     if (x_host) {
-        HIPCHK(c, hipMemcpyAsync(c->xin, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
-        *x = c->xin;
-        *f32 = false;
+        HIPCHK(c, hipMemcpyAsync(c->vec2, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, launch_scatter_slots(c->vec2, c->rank, c->d, c->vec1, 1, false, c->st));
+        *x = XView{c->vec1, 1, 0};
     } else {
-        *x = c->inst[inst].x;
-        *f32 = c->mixed;
+        *x = x_view(c, c->inst[inst]);
     }
     return ASAGA_OK;
 }
@@ -487,19 +525,13 @@ int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_o
 int asaga_updates(asaga_ctx* c, int64_t count) {
     if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
     if (count < 0) return fail(c, ASAGA_E_ARG, "negative update count");
-    if (c->inst.size() != 1) return fail(c, ASAGA_E_STATE, "asaga_updates needs a single-instance context");
+    if (c->d_insts) return fail(c, ASAGA_E_STATE, "asaga_updates needs a single-instance context");
     Inst& I = c->inst[0];
-    UpdateShape S;
-    S.serial = c->o.mode == ASAGA_MODE_SERIAL;
-    S.lanes = S.serial ? 64 : c->lanes;
-    S.waves = S.serial ? 1 : c->waves;
-    S.racy = c->o.racy != 0;
-    S.mixed = c->mixed;
     // serial launches are cut into pieces of at most 2^18 updates
-    const int64_t piece = S.serial ? ((int64_t)1 << 18) : count;
+    const int64_t piece = c->shape.serial ? ((int64_t)1 << 18) : count;
     for (int64_t done = 0; done < count;) {
         const int64_t k = count - done < piece ? count - done : piece;
-        HIPCHK(c, launch_updates(mat(c), inst_args(c, I, (uint64_t)I.t, (uint64_t)k), S, c->flag, c->st));
+        HIPCHK(c, launch_updates(mat(c), inst_args(I, (uint64_t)I.t, (uint64_t)k), c->shape, c->flag, c->st));
         I.t += k;
         done += k;
     }
@@ -509,30 +541,23 @@ int asaga_updates(asaga_ctx* c, int64_t count) {
 int asaga_epochs(asaga_ctx* c, int64_t n_epochs) {
     if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
     if (n_epochs < 0) return fail(c, ASAGA_E_ARG, "negative epoch count");
-    if (c->inst.size() == 1 && !c->d_insts) {
+    if (!c->d_insts) {
         for (int64_t e = 0; e < n_epochs; ++e) {
             int rc = asaga_updates(c, c->inst[0].m);
             if (rc) return rc;
         }
         return ASAGA_OK;
     }
-    UpdateShape S;
-    S.serial = false;
-    S.lanes = c->lanes;
-    S.waves = c->waves;
-    S.racy = false;
-    S.mixed = c->mixed;
     std::vector<InstArgs> h(c->inst.size());
     for (size_t k = 0; k < c->inst.size(); ++k) {
         const Inst& I = c->inst[k];
-        h[k] = inst_args(c, I, (uint64_t)I.t, (uint64_t)I.m);
+        h[k] = inst_args(I, (uint64_t)I.t, (uint64_t)I.m);
     }
     // the previous call's launches read the descriptors: wait before overwriting them
     HIPCHK(c, hipStreamSynchronize(c->st));
     HIPCHK(c, hipMemcpyAsync(c->d_insts, h.data(), h.size() * sizeof(InstArgs), hipMemcpyHostToDevice, c->st));
     for (int64_t e = 0; e < n_epochs; ++e)
-        HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), c->waves_per_inst, (uint64_t)e, S,
-                                         c->flag, c->st));
+        HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), (uint64_t)e, c->shape, c->flag, c->st));
     for (auto& I : c->inst) I.t += n_epochs * I.m;
     HIPCHK(c, hipStreamSynchronize(c->st));
     return ASAGA_OK;
@@ -544,14 +569,13 @@ int asaga_objective(asaga_ctx* c, int32_t inst, const double* x_host, double* f_
     int rc = check_inst(c, inst);
     if (rc) return rc;
     const Inst& I = c->inst[inst];
-    const void* x;
-    bool f32;
-    if ((rc = eval_x(c, inst, x_host, &x, &f32))) return rc;
+    XView x;
+    if ((rc = eval_x(c, inst, x_host, &x))) return rc;
     const MatArgs A = mat(c);
-    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, f32, c->z, c->st));
+    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, c->z, c->st));
     HIPCHK(c, launch_phi_terms(A, I.rows, I.m, c->z, c->tmp, c->st));
-    HIPCHK(c, launch_sum(c->tmp, I.m, false, c->part, c->scal + 0, c->st));
-    HIPCHK(c, launch_sum_x2(x, f32, c->d, c->part, c->scal + 1, c->st));
+    HIPCHK(c, launch_sum(c->tmp, I.m, c->part, c->scal + 0, c->st));
+    HIPCHK(c, launch_sum_x2(x, c->d, c->part, c->scal + 1, c->st));
     double s[2];
     HIPCHK(c, hipMemcpyAsync(s, c->scal, sizeof(s), hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -567,16 +591,17 @@ int asaga_full_grad(asaga_ctx* c, int32_t inst, const double* x_host, double* g_
     int rc = check_inst(c, inst);
     if (rc) return rc;
     const Inst& I = c->inst[inst];
-    const void* x;
-    bool f32;
-    if ((rc = eval_x(c, inst, x_host, &x, &f32))) return rc;
+    XView x;
+    if ((rc = eval_x(c, inst, x_host, &x))) return rc;
     const MatArgs A = mat(c);
-    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, f32, c->z, c->st));
+    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, c->z, c->st));
     HIPCHK(c, launch_dphi_coef(A, I.rows, I.m, c->z, 1.0 / (double)I.m, c->tmp, c->st));
-    HIPCHK(c, launch_fill_f64(c->vecd, 0.0, c->d, c->st));
-    HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, c->vecd, c->st));
-    HIPCHK(c, launch_axpy_x(x, f32, c->d, I.lambda, c->vecd, c->st));
-    HIPCHK(c, hipMemcpyAsync(g_host, c->vecd, c->d * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, launch_fill_f64(c->vec2, 0.0, c->d, 1, c->st));
+    HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, c->vec2, 1, c->st));
+    HIPCHK(c, launch_axpy_x(x, c->d, I.lambda, c->vec2, c->st));
+    // back to the caller's column order
+    HIPCHK(c, launch_gather_view(XView{c->vec2, 1, 0}, c->rank, c->d, c->vec1, c->st));
+    HIPCHK(c, hipMemcpyAsync(g_host, c->vec1, c->d * 8, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     return ASAGA_OK;
 }
@@ -587,12 +612,13 @@ int asaga_get_state(asaga_ctx* c, int32_t inst, double* x_host, double* alpha_ho
     if (rc) return rc;
     const Inst& I = c->inst[inst];
     if (x_host) {
-        if (c->mixed) {
-            HIPCHK(c, launch_widen_f32(static_cast<const float*>(I.x), c->d, c->vecd, c->st));
-            HIPCHK(c, hipMemcpyAsync(x_host, c->vecd, c->d * 8, hipMemcpyDeviceToHost, c->st));
-        } else {
-            HIPCHK(c, hipMemcpyAsync(x_host, I.x, c->d * 8, hipMemcpyDeviceToHost, c->st));
-        }
+        HIPCHK(c, launch_gather_view(x_view(c, I), c->rank, c->d, c->vec1, c->st));
+        HIPCHK(c, hipMemcpyAsync(x_host, c->vec1, c->d * 8, hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+    if (abar_host) {
+        HIPCHK(c, launch_gather_view(abar_view(I), c->rank, c->d, c->vec1, c->st));
+        HIPCHK(c, hipMemcpyAsync(abar_host, c->vec1, c->d * 8, hipMemcpyDeviceToHost, c->st));
         HIPCHK(c, hipStreamSynchronize(c->st));
     }
     if (alpha_host) {
@@ -603,7 +629,6 @@ int asaga_get_state(asaga_ctx* c, int32_t inst, double* x_host, double* alpha_ho
             HIPCHK(c, hipMemcpyAsync(alpha_host, I.alpha, I.m * 8, hipMemcpyDeviceToHost, c->st));
         }
     }
-    if (abar_host) HIPCHK(c, hipMemcpyAsync(abar_host, I.abar, c->d * 8, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (t_out) *t_out = I.t;
     return check_flag(c);
@@ -624,12 +649,13 @@ int asaga_set_state(asaga_ctx* c, int32_t inst, const double* x_host, const doub
     if (t_in && *t_in < 0) return fail(c, ASAGA_E_ARG, "negative sample counter");
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (x_host) {
-        if (c->mixed) {
-            HIPCHK(c, hipMemcpyAsync(c->vecd, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
-            HIPCHK(c, launch_narrow_f64(c->vecd, c->d, static_cast<float*>(I.x), c->st));
-        } else {
-            HIPCHK(c, hipMemcpyAsync(I.x, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
-        }
+        HIPCHK(c, hipMemcpyAsync(c->vec1, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+        if (c->mixed) HIPCHK(c, launch_scatter_slots(c->vec1, c->rank, c->d, I.xa, 4, true, c->st));
+        else HIPCHK(c, launch_scatter_slots(c->vec1, c->rank, c->d, I.xa, 2, false, c->st));
+    }
+    if (abar_host) {
+        HIPCHK(c, hipMemcpyAsync(c->vec2, abar_host, c->d * 8, hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, launch_scatter_slots(c->vec2, c->rank, c->d, I.xa + 1, 2, false, c->st));
     }
     if (alpha_host) {
         if (c->mixed) {
@@ -639,7 +665,6 @@ int asaga_set_state(asaga_ctx* c, int32_t inst, const double* x_host, const doub
             HIPCHK(c, hipMemcpyAsync(I.alpha, alpha_host, I.m * 8, hipMemcpyHostToDevice, c->st));
         }
     }
-    if (abar_host) HIPCHK(c, hipMemcpyAsync(I.abar, abar_host, c->d * 8, hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (t_in) I.t = *t_in;
     return ASAGA_OK;
@@ -650,8 +675,8 @@ int asaga_reanchor(asaga_ctx* c) {
     const MatArgs A = mat(c);
     for (auto& I : c->inst) {
         HIPCHK(c, launch_alpha_coef(I.alpha, c->mixed, I.m, 1.0 / (double)I.m, c->tmp, c->st));
-        HIPCHK(c, launch_fill_f64(I.abar, 0.0, c->d, c->st));
-        HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.abar, c->st));
+        HIPCHK(c, launch_fill_f64(I.xa + 1, 0.0, c->d, 2, c->st));
+        HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.xa + 1, 2, c->st));
     }
     return ASAGA_OK;
 }
@@ -668,9 +693,11 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->L = I.L;
     out->gamma = I.gamma;
     out->lambda = I.lambda;
-    out->waves = c->o.mode == ASAGA_MODE_SERIAL ? 1 : (c->d_insts ? c->waves_per_inst * (int)c->inst.size() : c->waves);
-    out->lanes_per_sample = c->o.mode == ASAGA_MODE_SERIAL ? 64 : c->lanes;
+    out->waves = c->shape.waves;
+    out->lanes_per_sample = c->shape.lanes;
     out->n_inst = (int32_t)c->inst.size();
+    out->hot_columns = c->shape.hot;
+    out->flush_every = c->shape.flush;
     out->reserved = 0;
     return ASAGA_OK;
 }

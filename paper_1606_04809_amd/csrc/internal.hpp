@@ -1,5 +1,12 @@
 // Internal interface between the C-ABI host code (asaga.hip) and the device
 // code (kernels.hip).  Not installed; not part of the public ABI.
+//
+// Device layout of one instance's state (columns relabelled by descending
+// count, so the most-used columns are 0, 1, 2, ...):
+//   xa[2c]     x_c     FP64 (mixed precision: FP32 in the low 4 bytes)
+//   xa[2c + 1] abar_c  FP64
+// so that one 16-byte pair holds everything a sample reads and writes for a
+// column, and two adjacent lanes reach both halves with one memory request.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,10 +18,9 @@ namespace asaga {
 // instance whose row list is the identity (rows == nullptr).
 struct InstArgs {
     const int32_t* rows;  // [m] training rows of the instance, or nullptr (= 0..n-1)
-    void* x;              // [d]  FP64 or FP32 iterate
+    double* xa;           // [2d] interleaved x / abar (layout above)
     void* alpha;          // [m]  FP64 or FP32 scalar memory, one per training row
-    double* abar;         // [d]  running average (1/m) sum_j alpha_j a_rows[j]
-    const double* D;      // [d]  m / cnt_v (0 for columns the instance never touches)
+    const double* D;      // [d]  m / cnt_c (0 for columns the instance never touches)
     int64_t m;            // number of training rows
     double gamma;
     double lambda;
@@ -26,7 +32,7 @@ struct InstArgs {
 
 struct MatArgs {
     const int64_t* rowptr;
-    const int32_t* colidx;
+    const int32_t* colidx;  // relabelled column indices
     const void* val;
     const double* b;
     int64_t n;
@@ -39,22 +45,36 @@ struct MatArgs {
 struct UpdateShape {
     int lanes;        // lanes per sample: 64, 32, 16 or 8
     int waves;        // wavefronts in flight (1 for serial)
+    int block;        // threads per workgroup
+    int hot;          // columns [0, hot) combined in LDS per workgroup (0: none)
+    int flush;        // samples per lane group between flushes of the LDS buffer
     bool serial;      // one wave, ordered: agent-scope fence between updates
     bool racy;        // plain read-modify-write (negative control)
     bool mixed;       // FP32 x and alpha
 };
 
+// A read-only view of a vector: element v at p[v * stride], FP64 or FP32.
+struct XView {
+    const void* p;
+    int64_t stride;
+    int32_t f32;
+};
+
 hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag, hipStream_t st);
-// Instance k applies samples t0_k + epoch*count_k .. t0_k + (epoch+1)*count_k - 1.
-hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, int n_inst, int waves_per_inst,
-                                  uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st);
+// Instance k applies samples t0_k + epoch*count_k .. t0_k + (epoch+1)*count_k - 1;
+// S.waves is the number of wavefronts per instance.
+hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, int n_inst, uint64_t epoch,
+                                  const UpdateShape& S, int* flag, hipStream_t st);
+size_t update_lds_bytes(const UpdateShape& S);
 
 // initialisation
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
-hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t st);
+hipError_t launch_fill_f64(double* p, double v, int64_t count, int64_t stride, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
 hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int32_t* cnt, hipStream_t st);
-// D_v = m / cnt_v (0 if cnt_v = 0); stats[0] = max cnt, stats[1] = min positive cnt
+// out[k] = rank[in[k]]
+hipError_t launch_relabel(const int32_t* in, int64_t nnz, const int32_t* rank, int32_t* out, hipStream_t st);
+// D_c = m / cnt_c (0 if cnt_c = 0); stats[0] = max cnt, stats[1] = min positive cnt
 hipError_t launch_reweight(const int32_t* cnt, int64_t d, int64_t m, double* D, int32_t* stats, hipStream_t st);
 // bits of max_i ||a_i||^2 over the rows into *maxbits (uint64 ordering of non-negative doubles)
 hipError_t launch_rownorm_max(const MatArgs& A, const int32_t* rows, int64_t m, unsigned long long* maxbits,
@@ -63,8 +83,7 @@ hipError_t launch_rownorm_max(const MatArgs& A, const int32_t* rows, int64_t m, 
 hipError_t launch_validate(const MatArgs& A, int64_t nnz, int32_t* bad, hipStream_t st);
 
 // evaluation: z_j = a_rows[j] . x
-hipError_t launch_rowdot(const MatArgs& A, const int32_t* rows, int64_t m, const void* x, bool x_f32, double* z,
-                         hipStream_t st);
+hipError_t launch_rowdot(const MatArgs& A, const int32_t* rows, int64_t m, XView x, double* z, hipStream_t st);
 // tmp_j = phi(z_j; b_rows[j])
 hipError_t launch_phi_terms(const MatArgs& A, const int32_t* rows, int64_t m, const double* z, double* tmp,
                             hipStream_t st);
@@ -73,16 +92,20 @@ hipError_t launch_dphi_coef(const MatArgs& A, const int32_t* rows, int64_t m, co
                             double* coef, hipStream_t st);
 // coef_j = alpha_j * scale
 hipError_t launch_alpha_coef(const void* alpha, bool f32, int64_t m, double scale, double* coef, hipStream_t st);
-// out_v += sum_j coef_j a_rows[j],v   (atomic FP64)
+// out[c * stride] += sum_j coef_j a_rows[j],c   (atomic FP64)
 hipError_t launch_scatter(const MatArgs& A, const int32_t* rows, int64_t m, const double* coef, double* out,
-                          hipStream_t st);
-// g_v += lambda x_v
-hipError_t launch_axpy_x(const void* x, bool x_f32, int64_t d, double lambda, double* g, hipStream_t st);
+                          int64_t stride, hipStream_t st);
+// g_c += lambda x_c
+hipError_t launch_axpy_x(XView x, int64_t d, double lambda, double* g, hipStream_t st);
 // sum of in[0..count) (two stages, pairwise over blocks) into *out; part needs kSumParts doubles
 constexpr int kSumParts = 1024;
-hipError_t launch_sum(const double* in, int64_t count, bool square, double* part, double* out, hipStream_t st);
-hipError_t launch_sum_x2(const void* x, bool x_f32, int64_t d, double* part, double* out, hipStream_t st);
-// conversions between the FP64 host-facing form and the state's storage type
+hipError_t launch_sum(const double* in, int64_t count, double* part, double* out, hipStream_t st);
+hipError_t launch_sum_x2(XView x, int64_t d, double* part, double* out, hipStream_t st);
+// out[v] = x[rank[v]]  (back to the caller's column order)
+hipError_t launch_gather_view(XView x, const int32_t* rank, int64_t d, double* out, hipStream_t st);
+// slot[rank[v] * stride] = in[v]  (into the relabelled order; f32 stores a float in the slot)
+hipError_t launch_scatter_slots(const double* in, const int32_t* rank, int64_t d, void* slot, int64_t stride, bool f32,
+                                hipStream_t st);
 hipError_t launch_widen_f32(const float* in, int64_t count, double* out, hipStream_t st);
 hipError_t launch_narrow_f64(const double* in, int64_t count, float* out, hipStream_t st);
 

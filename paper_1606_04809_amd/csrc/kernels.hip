@@ -4,21 +4,34 @@
 // SparseSAGA, with the projected L2 term of Section 4.2) applied lock-free by
 // many wavefronts at once, as Algorithm 2 describes: each sample reads x and
 // abar on its support without any lock (inconsistent reads), forms the dot
-// product, the scalar gradient change delta = phi'(z) - alpha_i, and adds its
-// update to x, abar and alpha_i with hardware atomic additions (Property 3).
+// product and the scalar gradient change delta = phi'(z) - alpha_i, and adds
+// its update to x, abar and alpha_i with atomic additions (Property 3).
 //
-// Mapping to CDNA (64-wide wavefronts):
-//   * a group of G lanes (G = 64, 32, 16 or 8) owns one sample at a time, so a
-//     wavefront carries 64/G samples; the sample index comes from a
-//     counter-based stream, so no queue or global counter is needed;
-//   * the row's column indices and values stream in coalesced, G entries per
-//     load instruction; up to 128 entries per row stay in registers between
-//     the read phase and the write phase;
-//   * x, abar and D are gathered per entry; x and abar with relaxed
-//     agent-scope atomic loads (coherent across the XCDs' L2 caches), D with
-//     plain loads (read-only, cacheable);
-//   * the dot product is reduced inside the group with cross-lane shuffles;
-//   * the scatter uses global FP64/FP32 atomic add (no return value).
+// Mapping to CDNA4 (64-wide wavefronts).  Measured on MI355X: the L2 atomic
+// unit serves about 2.3e10 requests/s, where one request is one wave
+// instruction's lanes that fall in one 64-byte line (up to 8 FP64 adds), and
+// a single address takes at most 8.3e7 atomics/s.  Hence:
+//   * a group of G lanes (64, 32, 16 or 8) owns one sample; the sample index
+//     comes from a counter-based stream, so no queue or global counter, and
+//     the next sample's row bounds are fetched while the current one runs;
+//   * the read phase gathers x_c with one lane per row entry; the dot product
+//     is reduced inside the group with cross-lane shuffles;
+//   * the write phase works in lane pairs, one row entry per pair: the even
+//     lane carries x_c, the odd lane abar_c.  x and abar are interleaved per
+//     column (16 bytes), so the pair's load and the pair's atomic add are
+//     each one memory request;
+//   * the row's column indices and values stream in coalesced and are read
+//     again (from cache) in the write phase instead of being held in
+//     registers, so that many wavefronts fit on a CU;
+//   * columns are relabelled by descending count, so the most-used columns
+//     are [0, H).  Each workgroup keeps them in LDS: a view of the global
+//     values and its own pending additions (LDS atomics run at ~1e12/s).
+//     Every F samples per group the workgroup adds its pending sums to the
+//     global state with line-coalesced atomics and refreshes the view from
+//     the values those atomics return.  Reads of hot columns touch only LDS;
+//     this removes the per-line serialisation of the columns every row
+//     touches, and the L2 tag stalls of reading lines with atomics in
+//     flight (atomics execute at the memory side on MI355X).
 // There is no matrix-core work: the update is a sparse gather/scatter.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -27,6 +40,11 @@
 #include "internal.hpp"
 
 namespace asaga {
+
+// LDS of a workgroup with a hot set of H columns, both halves interleaved
+// like xa:  lds[0, 2H)   view: the global (x, abar) values at the last flush
+//           lds[2H, 4H)  pend: the workgroup's own additions since then
+extern __shared__ double lds[];
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -68,16 +86,28 @@ __device__ __forceinline__ double dphi(double z, double b, int loss) {
     return -b / (1.0 + exp(m));
 }
 
-// Shared-state access.  Relaxed atomics at agent scope: no ordering, but the
-// value read is the one in the device-coherent level, not a stale line of
-// another XCD's L2.
-template <typename T>
-__device__ __forceinline__ T load_state(const T* p) {
-    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Shared-state reads: relaxed atomics at agent scope (no ordering; the value
+// comes from the device-coherent level).  comp 0 reads x_c, comp 1 abar_c.
+template <bool MIXED>
+__device__ __forceinline__ double load_slot(const double* xa, int32_t c, int comp) {
+    const uint64_t bits = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<double*>(xa)) + 2 * (int64_t)c + comp,
+                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (MIXED && comp == 0) return (double)__uint_as_float((uint32_t)bits);
+    return __longlong_as_double((long long)bits);
+}
+
+template <bool MIXED>
+__device__ __forceinline__ double load_alpha(const void* alpha, int64_t j) {
+    if constexpr (MIXED)
+        return (double)__hip_atomic_load(const_cast<float*>(static_cast<const float*>(alpha)) + j, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    else
+        return __hip_atomic_load(const_cast<double*>(static_cast<const double*>(alpha)) + j, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool RACY, typename T>
-__device__ __forceinline__ void add_state(T* p, T v) {
+__device__ __forceinline__ void add_global(T* p, T v) {
     if constexpr (RACY) {
         // non-thread-safe read-modify-write (negative control)
         const T o = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -85,6 +115,27 @@ __device__ __forceinline__ void add_state(T* p, T v) {
     } else {
         __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// add w to slot (c, comp) of the state: LDS pending sum for hot columns,
+// global atomic otherwise
+template <bool RACY, bool MIXED>
+__device__ __forceinline__ void add_slot(double* xa, int32_t c, int comp, int hot, double w) {
+    if (c < hot) {
+        atomicAdd(&lds[2 * hot + 2 * c + comp], w);
+    } else if (MIXED && comp == 0) {
+        add_global<RACY, float>(reinterpret_cast<float*>(xa + 2 * (int64_t)c), (float)w);
+    } else {
+        add_global<RACY, double>(xa + 2 * (int64_t)c + comp, w);
+    }
+}
+
+template <bool RACY, bool MIXED>
+__device__ __forceinline__ void add_alpha(void* alpha, int64_t j, double delta) {
+    if constexpr (MIXED)
+        add_global<RACY, float>(static_cast<float*>(alpha) + j, (float)delta);
+    else
+        add_global<RACY, double>(static_cast<double*>(alpha) + j, delta);
 }
 
 // sum over the G lanes of a group (G a power of two dividing 64)
@@ -99,119 +150,277 @@ __device__ __forceinline__ double group_sum(double v) {
 // the Sparse SAGA update of one sample, applied by a group of G lanes
 // ---------------------------------------------------------------------------
 
-template <int G, bool SERIAL, bool RACY, typename VT, typename XT>
-__device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I, uint64_t t, int gl, int* flag) {
-    constexpr int R = 128 / G;  // entries per lane kept in registers (rows up to 128 entries)
+// The (x_c, abar_c) pair of column c: one 16-byte load with the sc1 cache
+// policy (served from the device-coherent level, like an agent-scope
+// atomic load), through a buffer descriptor whose range check returns zeros
+// for an offset past the state (the CDNA descriptor word 3 is 0x00020000).
+struct Pair {
+    double x, a;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const double* xa, int64_t d) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(xa), (short)0, (int)(d * 16), 0x00020000);
+}
+
+// Columns below `hot` are served from LDS: their load gets an offset past
+// the descriptor's range, which the hardware drops (it returns zeros and
+// sends no request), so the read needs no branch.
+template <bool MIXED>
+__device__ __forceinline__ Pair load_pair(__amdgpu_buffer_rsrc_t r, int32_t c, int hot) {
+    constexpr int kSC1 = 16;
+    const int off = c >= hot ? c * 16 : (int)0x7ffffff0;
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kSC1);
+    Pair p;
+    if (MIXED) p.x = (double)__uint_as_float(v[0]);
+    else p.x = __longlong_as_double((long long)(((uint64_t)v[1] << 32) | v[0]));
+    p.a = __longlong_as_double((long long)(((uint64_t)v[3] << 32) | v[2]));
+    return p;
+}
+
+// Row of one sample: j (index into the instance's rows), i (matrix row),
+// bounds, label, and (asynchronous mode) an early read of alpha_j.
+struct RowRef {
+    int64_t j, i, rs, re;
+    double b, alpha;
+};
+
+template <bool SERIAL, bool MIXED>
+__device__ __forceinline__ RowRef row_ref(const MatArgs& A, const InstArgs& I, uint64_t t) {
+    RowRef r;
+    r.j = sample_index(I.seed, t, I.m);
+    r.i = I.rows ? (int64_t)I.rows[r.j] : r.j;
+    r.rs = A.rowptr[r.i];
+    r.re = A.rowptr[r.i + 1];
+    r.b = A.b[r.i];
+    r.alpha = SERIAL ? 0.0 : load_alpha<MIXED>(I.alpha, r.j);
+    return r;
+}
+
+// Sample j is processed by one group of G lanes working in pairs: the pair
+// (2e, 2e+1) takes the row entries e, e + G/2, e + G, ...  Both lanes of a
+// pair load the entry's column, value and (x_c, abar_c) pair (one request
+// each for the pair); the even lane adds a_c x_hat_c to the dot product and
+// later adds the x step, the odd lane adds the abar step.  Rows of up to
+// P * G / 2 entries are held in registers between the two phases, with all
+// their loads issued together; longer rows are processed in chunks and read
+// again for the write phase.
+template <int G, int P, bool SERIAL, bool RACY, bool MIXED, typename VT>
+__device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I, const RowRef& rr, int gl, int hot,
+                                             int* flag) {
+    constexpr int E = G / 2;
+    constexpr int CAP = P * E;
+    const int comp = gl & 1;
+    const int e = gl >> 1;
     const VT* __restrict__ val = static_cast<const VT*>(A.val);
-    XT* x = static_cast<XT*>(I.x);
-    XT* alpha = static_cast<XT*>(I.alpha);
+    const __amdgpu_buffer_rsrc_t rsrc = state_rsrc(I.xa, A.d);
+    const int64_t len = rr.re - rr.rs;
 
-    // sample (Algorithm 2: sample first, then read only the support)
-    const int64_t j = sample_index(I.seed, t, I.m);
-    const int64_t i = I.rows ? (int64_t)I.rows[j] : j;
-    const int64_t rs = A.rowptr[i];
-    const int64_t re = A.rowptr[i + 1];
-
-    // read phase: x_hat, abar and D on S_i; partial dot product
-    int32_t cc[R];
-    double vv[R], xx[R], aa[R], dd[R];
+    // read phase
+    int32_t cc[P];
+    double vv[P], xs[P], as[P], dd[P];
     double zp = 0.0;
+    if (len <= CAP) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t k = rs + gl + (int64_t)r * G;
-        if (k < re) {
+        for (int p = 0; p < P; ++p) {
+            const int64_t q = (int64_t)p * E + e;
+            const int64_t k = rr.rs + (q < len ? q : 0);  // idle lanes re-read entry 0
+            cc[p] = A.colidx[k];
+            vv[p] = widen(val[k]);
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const Pair pr = load_pair<MIXED>(rsrc, cc[p], hot);
+            xs[p] = pr.x;
+            as[p] = pr.a;
+            dd[p] = I.D[cc[p]];
+        }
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const int64_t q = (int64_t)p * E + e;
+            if (q < len) {
+                if (cc[p] < hot) {
+                    const int h = 2 * cc[p];
+                    xs[p] = lds[h] + lds[2 * hot + h];
+                    as[p] = lds[h + 1] + lds[2 * hot + h + 1];
+                }
+                if (comp == 0) zp += vv[p] * xs[p];
+            }
+        }
+    } else {
+        for (int64_t k = rr.rs + gl; k < rr.re; k += G) {
             const int32_t c = A.colidx[k];
-            cc[r] = c;
-            vv[r] = widen(val[k]);
-            xx[r] = (double)load_state(x + c);
-            aa[r] = load_state(I.abar + c);
-            dd[r] = I.D[c];
-            zp += vv[r] * xx[r];
+            double x = load_pair<MIXED>(rsrc, c, hot).x;
+            if (c < hot) x = lds[2 * c] + lds[2 * hot + 2 * c];
+            zp += widen(val[k]) * x;
         }
     }
-    for (int64_t k = rs + gl + (int64_t)R * G; k < re; k += G) zp += widen(val[k]) * (double)load_state(x + A.colidx[k]);
     const double z = group_sum<G>(zp);
 
     // scalar gradient change against the memory
-    double g = dphi(z, A.b[i], A.loss);
-    if constexpr (sizeof(XT) == 4) g = (double)(float)g;  // stored memory is FP32: delta exact in FP64
-    const double delta = g - (double)load_state(alpha + j);
+    double g = dphi(z, rr.b, A.loss);
+    if constexpr (MIXED) g = (double)(float)g;  // stored memory is FP32: delta exact in FP64
+    const double al = SERIAL ? load_alpha<MIXED>(I.alpha, rr.j) : rr.alpha;
+    const double delta = g - al;
     if (gl == 0 && !isfinite(delta)) *flag = 1;
 
-    // write phase: x_v -= gamma (delta a_v + D_v (abar_v + lambda x_hat_v)); abar_v += delta a_v / m
+    // write phase: x_c += -gamma (delta a_c + D_c (abar_c + lambda x_hat_c)) on even lanes,
+    //              abar_c += delta a_c / m on odd lanes
     const double gam = I.gamma, lam = I.lambda, dm = delta * I.inv_m;
+    if (len <= CAP) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int64_t k = rs + gl + (int64_t)r * G;
-        if (k < re) {
-            const double step = -gam * (delta * vv[r] + dd[r] * (aa[r] + lam * xx[r]));
-            add_state<RACY>(x + cc[r], (XT)step);
-            add_state<RACY>(I.abar + cc[r], dm * vv[r]);
+        for (int p = 0; p < P; ++p) {
+            const int64_t q = (int64_t)p * E + e;
+            if (q < len) {
+                const double w = comp == 0 ? -gam * (delta * vv[p] + dd[p] * (as[p] + lam * xs[p])) : dm * vv[p];
+                add_slot<RACY, MIXED>(I.xa, cc[p], comp, hot, w);
+            }
+        }
+    } else {
+        for (int64_t k = rr.rs + e; k < rr.re; k += E) {
+            const int32_t c = A.colidx[k];
+            const double v = widen(val[k]);
+            Pair pr = load_pair<MIXED>(rsrc, c, hot);
+            if (c < hot) {
+                pr.x = lds[2 * c] + lds[2 * hot + 2 * c];
+                pr.a = lds[2 * c + 1] + lds[2 * hot + 2 * c + 1];
+            }
+            const double w = comp == 0 ? -gam * (delta * v + I.D[c] * (pr.a + lam * pr.x)) : dm * v;
+            add_slot<RACY, MIXED>(I.xa, c, comp, hot, w);
         }
     }
-    for (int64_t k = rs + gl + (int64_t)R * G; k < re; k += G) {
-        const int32_t c = A.colidx[k];
-        const double v = widen(val[k]);
-        const double xo = (double)load_state(x + c);
-        const double ab = load_state(I.abar + c);
-        const double step = -gam * (delta * v + I.D[c] * (ab + lam * xo));
-        add_state<RACY>(x + c, (XT)step);
-        add_state<RACY>(I.abar + c, dm * v);
-    }
-    if (gl == 0) add_state<RACY>(alpha + j, (XT)delta);
+    if (gl == 0) add_alpha<RACY, MIXED>(I.alpha, rr.j, delta);
     if constexpr (SERIAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 
-// One instance: updates t0 .. t0+count-1, sample slot s = wave*(64/G) + group,
-// strided by the number of slots in the grid.
-template <int G, bool SERIAL, bool RACY, typename VT, typename XT>
-__global__ void __launch_bounds__(256) k_update(MatArgs A, InstArgs I, int* flag) {
-    constexpr int SPW = 64 / G;
-    const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint64_t slots = (((uint64_t)gridDim.x * blockDim.x) >> 6) * SPW;
-    for (uint64_t s = wave * SPW + (uint64_t)(lane / G); s < I.count; s += slots)
-        apply_update<G, SERIAL, RACY, VT, XT>(A, I, I.t0 + s, lane & (G - 1), flag);
+// Add the workgroup's pending sums of the hot columns to the global state,
+// clear them, and refresh the view: a slot with a pending sum takes the value
+// its returning atomic add reports plus the sum, any other slot is read
+// again.  Consecutive threads take consecutive slots, so each wave
+// instruction covers 512 contiguous bytes (8 lines).
+template <bool MIXED>
+__device__ __forceinline__ void flush_and_refresh(double* xa, int hot) {
+    for (int q = threadIdx.x; q < 2 * hot; q += blockDim.x) {
+        const double w = lds[2 * hot + q];
+        double now;
+        if (MIXED && (q & 1) == 0) {
+            float* p = reinterpret_cast<float*>(xa + q);
+            now = w != 0.0 ? (double)(__hip_atomic_fetch_add(p, (float)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                                      (float)w)
+                           : (double)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            now = w != 0.0 ? __hip_atomic_fetch_add(xa + q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + w
+                           : __hip_atomic_load(xa + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        lds[q] = now;
+        lds[2 * hot + q] = 0.0;
+    }
 }
 
-// Many instances in one persistent grid: waves_per_inst consecutive
-// wavefronts serve one instance.
-template <int G, typename VT, typename XT>
-__global__ void __launch_bounds__(256) k_update_batched(MatArgs A, const InstArgs* insts, int n_inst, int wpi,
-                                                        uint64_t epoch, int* flag) {
-    constexpr int SPW = 64 / G;
-    const int lane = threadIdx.x & 63;
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int inst = (int)(wave / (uint64_t)wpi);
+template <bool MIXED>
+__device__ __forceinline__ void load_view(const double* xa, int hot) {
+    for (int q = threadIdx.x; q < 2 * hot; q += blockDim.x) {
+        double now;
+        if (MIXED && (q & 1) == 0)
+            now = (double)__hip_atomic_load(reinterpret_cast<float*>(const_cast<double*>(xa) + q), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        else
+            now = __hip_atomic_load(const_cast<double*>(xa) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        lds[q] = now;
+        lds[2 * hot + q] = 0.0;
+    }
+}
+
+// The samples of one launch for one instance, spread over `slots` lane
+// groups: group `slot` applies samples s = slot + k * slots, k = 0, 1, ...
+// The row bounds of the next sample are fetched while the current one is
+// processed.  With a hot set, all groups of the workgroup advance in rounds
+// of `flush` samples and the workgroup flushes its LDS sums after each round.
+template <int G, int P, bool SERIAL, bool RACY, bool MIXED, typename VT>
+__device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, uint64_t t0, uint64_t slot,
+                                          uint64_t slots, int hot, int flush, int* flag) {
+    const int gl = threadIdx.x & (G - 1);
+    const uint64_t kmax = (I.count + slots - 1) / slots;
+    if (hot > 0) {
+        load_view<MIXED>(I.xa, hot);
+        __syncthreads();
+    }
+    const uint64_t round = hot > 0 ? (uint64_t)flush : kmax;
+    RowRef cur{0, 0, 0, 0, 0.0, 0.0};
+    if (slot < I.count) cur = row_ref<SERIAL, MIXED>(A, I, t0 + slot);
+    for (uint64_t k0 = 0; k0 < kmax; k0 += round) {
+        const uint64_t k1 = k0 + round < kmax ? k0 + round : kmax;
+        for (uint64_t k = k0; k < k1; ++k) {
+            const uint64_t s = slot + k * slots;
+            const uint64_t s2 = s + slots;
+            RowRef nxt{0, 0, 0, 0, 0.0, 0.0};
+            if (s2 < I.count) nxt = row_ref<SERIAL, MIXED>(A, I, t0 + s2);
+            if (s < I.count) apply_update<G, P, SERIAL, RACY, MIXED, VT>(A, I, cur, gl, hot, flag);
+            cur = nxt;
+        }
+        if (hot > 0) {
+            __syncthreads();
+            flush_and_refresh<MIXED>(I.xa, hot);
+            __syncthreads();
+        }
+    }
+}
+
+// P = 4 passes in registers: rows of up to 2G entries take the fast path.
+constexpr int kPasses = 4;
+
+template <int G, bool SERIAL, bool RACY, bool MIXED, typename VT>
+__global__ void __launch_bounds__(512) k_update(MatArgs A, InstArgs I, int hot, int flush, int* flag) {
+    const uint64_t groups = blockDim.x / G;
+    const uint64_t slot = blockIdx.x * groups + threadIdx.x / G;
+    const uint64_t slots = (uint64_t)gridDim.x * groups;
+    run_slots<G, kPasses, SERIAL, RACY, MIXED, VT>(A, I, I.t0, slot, slots, hot, flush, flag);
+}
+
+// Many instances in one persistent grid: blocks_per_inst consecutive
+// workgroups serve one instance.
+template <int G, bool MIXED, typename VT>
+__global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArgs* insts, int n_inst,
+                                                        int blocks_per_inst, uint64_t epoch, int hot, int flush,
+                                                        int* flag) {
+    const int inst = (int)(blockIdx.x / (unsigned)blocks_per_inst);
     if (inst >= n_inst) return;
     const InstArgs I = insts[inst];
-    const uint64_t lw = wave % (uint64_t)wpi;
-    const uint64_t slots = (uint64_t)wpi * SPW;
-    const uint64_t t0 = I.t0 + epoch * I.count;
-    for (uint64_t s = lw * SPW + (uint64_t)(lane / G); s < I.count; s += slots)
-        apply_update<G, false, false, VT, XT>(A, I, t0 + s, lane & (G - 1), flag);
+    const uint64_t groups = blockDim.x / G;
+    const uint64_t slot = (blockIdx.x % (unsigned)blocks_per_inst) * groups + threadIdx.x / G;
+    const uint64_t slots = (uint64_t)blocks_per_inst * groups;
+    run_slots<G, kPasses, false, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, hot, flush, flag);
 }
 
 // ---------------------------------------------------------------------------
 // launchers for the update kernels
 // ---------------------------------------------------------------------------
 
-template <typename VT, typename XT>
+size_t update_lds_bytes(const UpdateShape& S) { return (size_t)S.hot * 4 * sizeof(double); }
+
+template <bool MIXED, typename VT>
 static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag,
                                    hipStream_t st) {
     if (I.count == 0) return hipSuccess;
     if (S.serial) {
-        k_update<64, true, false, VT, XT><<<1, 64, 0, st>>>(A, I, flag);
+        k_update<64, true, false, MIXED, VT><<<1, 64, 0, st>>>(A, I, 0, 1, flag);
         return hipGetLastError();
     }
-    const int threads = 256;
+    const int threads = S.block;
     const int blocks = (S.waves * 64 + threads - 1) / threads;
-#define ASAGA_LAUNCH(GG)                                                                   \
-    case GG:                                                                               \
-        if (S.racy)                                                                        \
-            k_update<GG, false, true, VT, XT><<<blocks, threads, 0, st>>>(A, I, flag);     \
-        else                                                                               \
-            k_update<GG, false, false, VT, XT><<<blocks, threads, 0, st>>>(A, I, flag);    \
+    const size_t lds = update_lds_bytes(S);
+#define ASAGA_LAUNCH(GG)                                                                                     \
+    case GG:                                                                                                 \
+        if (S.racy) {                                                                                        \
+            k_update<GG, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, 0, 1, flag);             \
+        } else {                                                                                             \
+            if (lds > 65536) {                                                                               \
+                const hipError_t e = hipFuncSetAttribute(                                                    \
+                    reinterpret_cast<const void*>(&k_update<GG, false, false, MIXED, VT>),                   \
+                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                                   \
+                if (e != hipSuccess) return e;                                                               \
+            }                                                                                                \
+            k_update<GG, false, false, MIXED, VT><<<blocks, threads, lds, st>>>(A, I, S.hot, S.flush, flag); \
+        }                                                                                                    \
         break;
     switch (S.lanes) {
         ASAGA_LAUNCH(64)
@@ -227,46 +436,58 @@ static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const Up
 hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag, hipStream_t st) {
     switch (A.val_dtype) {
         case ASAGA_VAL_F64:
-            return S.mixed ? launch_updates_t<double, float>(A, I, S, flag, st)
-                           : launch_updates_t<double, double>(A, I, S, flag, st);
+            return S.mixed ? launch_updates_t<true, double>(A, I, S, flag, st)
+                           : launch_updates_t<false, double>(A, I, S, flag, st);
         case ASAGA_VAL_F32:
-            return S.mixed ? launch_updates_t<float, float>(A, I, S, flag, st)
-                           : launch_updates_t<float, double>(A, I, S, flag, st);
+            return S.mixed ? launch_updates_t<true, float>(A, I, S, flag, st)
+                           : launch_updates_t<false, float>(A, I, S, flag, st);
         case ASAGA_VAL_BF16:
-            return S.mixed ? launch_updates_t<uint16_t, float>(A, I, S, flag, st)
-                           : launch_updates_t<uint16_t, double>(A, I, S, flag, st);
+            return S.mixed ? launch_updates_t<true, uint16_t>(A, I, S, flag, st)
+                           : launch_updates_t<false, uint16_t>(A, I, S, flag, st);
     }
     return hipErrorInvalidValue;
 }
 
-template <typename VT, typename XT>
-static hipError_t launch_batched_t(const MatArgs& A, const InstArgs* insts, int n_inst, int wpi, uint64_t epoch,
+template <int G, bool MIXED, typename VT>
+static hipError_t launch_batched_g(const MatArgs& A, const InstArgs* insts, int n_inst, uint64_t epoch,
                                    const UpdateShape& S, int* flag, hipStream_t st) {
-    const int threads = 256;
-    const int64_t waves = (int64_t)n_inst * wpi;
-    const int blocks = (int)((waves * 64 + threads - 1) / threads);
-    switch (S.lanes) {
-        case 64: k_update_batched<64, VT, XT><<<blocks, threads, 0, st>>>(A, insts, n_inst, wpi, epoch, flag); break;
-        case 32: k_update_batched<32, VT, XT><<<blocks, threads, 0, st>>>(A, insts, n_inst, wpi, epoch, flag); break;
-        case 16: k_update_batched<16, VT, XT><<<blocks, threads, 0, st>>>(A, insts, n_inst, wpi, epoch, flag); break;
-        case 8: k_update_batched<8, VT, XT><<<blocks, threads, 0, st>>>(A, insts, n_inst, wpi, epoch, flag); break;
-        default: return hipErrorInvalidValue;
+    const int threads = S.block;
+    const int bpi = (S.waves * 64 + threads - 1) / threads;
+    const int blocks = bpi * n_inst;
+    const size_t lds = update_lds_bytes(S);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_batched<G, MIXED, VT>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
     }
+    k_update_batched<G, MIXED, VT><<<blocks, threads, lds, st>>>(A, insts, n_inst, bpi, epoch, S.hot, S.flush, flag);
     return hipGetLastError();
 }
 
-hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, int n_inst, int waves_per_inst,
-                                  uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
+template <bool MIXED, typename VT>
+static hipError_t launch_batched_t(const MatArgs& A, const InstArgs* insts, int n_inst, uint64_t epoch,
+                                   const UpdateShape& S, int* flag, hipStream_t st) {
+    switch (S.lanes) {
+        case 64: return launch_batched_g<64, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
+        case 32: return launch_batched_g<32, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
+        case 16: return launch_batched_g<16, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
+        case 8: return launch_batched_g<8, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, int n_inst, uint64_t epoch,
+                                  const UpdateShape& S, int* flag, hipStream_t st) {
     switch (A.val_dtype) {
         case ASAGA_VAL_F64:
-            return S.mixed ? launch_batched_t<double, float>(A, dev_insts, n_inst, waves_per_inst, epoch, S, flag, st)
-                           : launch_batched_t<double, double>(A, dev_insts, n_inst, waves_per_inst, epoch, S, flag, st);
+            return S.mixed ? launch_batched_t<true, double>(A, dev_insts, n_inst, epoch, S, flag, st)
+                           : launch_batched_t<false, double>(A, dev_insts, n_inst, epoch, S, flag, st);
         case ASAGA_VAL_F32:
-            return S.mixed ? launch_batched_t<float, float>(A, dev_insts, n_inst, waves_per_inst, epoch, S, flag, st)
-                           : launch_batched_t<float, double>(A, dev_insts, n_inst, waves_per_inst, epoch, S, flag, st);
+            return S.mixed ? launch_batched_t<true, float>(A, dev_insts, n_inst, epoch, S, flag, st)
+                           : launch_batched_t<false, float>(A, dev_insts, n_inst, epoch, S, flag, st);
         case ASAGA_VAL_BF16:
-            return S.mixed ? launch_batched_t<uint16_t, float>(A, dev_insts, n_inst, waves_per_inst, epoch, S, flag, st)
-                           : launch_batched_t<uint16_t, double>(A, dev_insts, n_inst, waves_per_inst, epoch, S, flag, st);
+            return S.mixed ? launch_batched_t<true, uint16_t>(A, dev_insts, n_inst, epoch, S, flag, st)
+                           : launch_batched_t<false, uint16_t>(A, dev_insts, n_inst, epoch, S, flag, st);
     }
     return hipErrorInvalidValue;
 }
@@ -283,24 +504,24 @@ static inline int grid_for(int64_t items, int threads, int cap = 65536) {
 }
 
 template <typename T>
-__global__ void k_fill(T* p, T v, int64_t count) {
+__global__ void k_fill(T* p, T v, int64_t count, int64_t stride) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
-        p[k] = v;
+        p[k * stride] = v;
 }
 
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    k_fill<int32_t><<<grid_for(count, 256), 256, 0, st>>>(p, v, count);
+    k_fill<int32_t><<<grid_for(count, 256), 256, 0, st>>>(p, v, count, 1);
     return hipGetLastError();
 }
-hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t st) {
+hipError_t launch_fill_f64(double* p, double v, int64_t count, int64_t stride, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    k_fill<double><<<grid_for(count, 256), 256, 0, st>>>(p, v, count);
+    k_fill<double><<<grid_for(count, 256), 256, 0, st>>>(p, v, count, stride);
     return hipGetLastError();
 }
 hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    k_fill<float><<<grid_for(count, 256), 256, 0, st>>>(p, v, count);
+    k_fill<float><<<grid_for(count, 256), 256, 0, st>>>(p, v, count, 1);
     return hipGetLastError();
 }
 
@@ -324,6 +545,17 @@ hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int
     return hipGetLastError();
 }
 
+__global__ void k_relabel(const int32_t* in, int64_t nnz, const int32_t* rank, int32_t* out) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = rank[in[k]];
+}
+
+hipError_t launch_relabel(const int32_t* in, int64_t nnz, const int32_t* rank, int32_t* out, hipStream_t st) {
+    if (nnz <= 0) return hipSuccess;
+    k_relabel<<<grid_for(nnz, 256), 256, 0, st>>>(in, nnz, rank, out);
+    return hipGetLastError();
+}
+
 __global__ void k_reweight(const int32_t* cnt, int64_t d, int64_t m, double* D, int32_t* stats) {
     int32_t mx = 0, mn = 0x7fffffff;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d; v += (int64_t)gridDim.x * blockDim.x) {
@@ -341,6 +573,9 @@ hipError_t launch_reweight(const int32_t* cnt, int64_t d, int64_t m, double* D, 
     return hipGetLastError();
 }
 
+// sum over the kRowLanes lanes of a row group
+__device__ __forceinline__ double row_sum(double v) { return group_sum<kRowLanes>(v); }
+
 template <typename VT>
 __global__ void k_rownorm_max(MatArgs A, const int32_t* rows, int64_t m, unsigned long long* maxbits) {
     const VT* val = static_cast<const VT*>(A.val);
@@ -355,7 +590,7 @@ __global__ void k_rownorm_max(MatArgs A, const int32_t* rows, int64_t m, unsigne
             const double v = widen(val[k]);
             s += v * v;
         }
-        s = group_sum<kRowLanes>(s);
+        s = row_sum(s);
         if (s > best) best = s;
     }
     if (gl == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(best));
@@ -415,8 +650,12 @@ hipError_t launch_validate(const MatArgs& A, int64_t nnz, int32_t* bad, hipStrea
 // evaluation kernels (objective, gradient, re-anchoring of abar)
 // ---------------------------------------------------------------------------
 
-template <typename VT, typename XT>
-__global__ void k_rowdot(MatArgs A, const int32_t* rows, int64_t m, const XT* x, double* z) {
+__device__ __forceinline__ double xget(const XView& X, int64_t v) {
+    return X.f32 ? (double)static_cast<const float*>(X.p)[v * X.stride] : static_cast<const double*>(X.p)[v * X.stride];
+}
+
+template <typename VT>
+__global__ void k_rowdot(MatArgs A, const int32_t* rows, int64_t m, XView x, double* z) {
     const VT* val = static_cast<const VT*>(A.val);
     const int gl = threadIdx.x & (kRowLanes - 1);
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
@@ -424,30 +663,21 @@ __global__ void k_rowdot(MatArgs A, const int32_t* rows, int64_t m, const XT* x,
     for (int64_t j = grp; j < m; j += ngrp) {
         const int64_t i = row_of(rows, j);
         double s = 0.0;
-        for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes)
-            s += widen(val[k]) * (double)x[A.colidx[k]];
-        s = group_sum<kRowLanes>(s);
+        for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes) s += widen(val[k]) * xget(x, A.colidx[k]);
+        s = row_sum(s);
         if (gl == 0) z[j] = s;
     }
 }
 
-template <typename XT>
-static hipError_t launch_rowdot_x(const MatArgs& A, const int32_t* rows, int64_t m, const XT* x, double* z,
-                                  hipStream_t st) {
+hipError_t launch_rowdot(const MatArgs& A, const int32_t* rows, int64_t m, XView x, double* z, hipStream_t st) {
     const int blocks = grid_for(m * kRowLanes, 256);
     switch (A.val_dtype) {
-        case ASAGA_VAL_F64: k_rowdot<double, XT><<<blocks, 256, 0, st>>>(A, rows, m, x, z); break;
-        case ASAGA_VAL_F32: k_rowdot<float, XT><<<blocks, 256, 0, st>>>(A, rows, m, x, z); break;
-        case ASAGA_VAL_BF16: k_rowdot<uint16_t, XT><<<blocks, 256, 0, st>>>(A, rows, m, x, z); break;
+        case ASAGA_VAL_F64: k_rowdot<double><<<blocks, 256, 0, st>>>(A, rows, m, x, z); break;
+        case ASAGA_VAL_F32: k_rowdot<float><<<blocks, 256, 0, st>>>(A, rows, m, x, z); break;
+        case ASAGA_VAL_BF16: k_rowdot<uint16_t><<<blocks, 256, 0, st>>>(A, rows, m, x, z); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-hipError_t launch_rowdot(const MatArgs& A, const int32_t* rows, int64_t m, const void* x, bool x_f32, double* z,
-                         hipStream_t st) {
-    return x_f32 ? launch_rowdot_x<float>(A, rows, m, static_cast<const float*>(x), z, st)
-                 : launch_rowdot_x<double>(A, rows, m, static_cast<const double*>(x), z, st);
 }
 
 __global__ void k_phi_terms(MatArgs A, const int32_t* rows, int64_t m, const double* z, double* tmp) {
@@ -487,7 +717,7 @@ hipError_t launch_alpha_coef(const void* alpha, bool f32, int64_t m, double scal
 }
 
 template <typename VT>
-__global__ void k_scatter(MatArgs A, const int32_t* rows, int64_t m, const double* coef, double* out) {
+__global__ void k_scatter(MatArgs A, const int32_t* rows, int64_t m, const double* coef, double* out, int64_t stride) {
     const VT* val = static_cast<const VT*>(A.val);
     const int gl = threadIdx.x & (kRowLanes - 1);
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
@@ -496,33 +726,30 @@ __global__ void k_scatter(MatArgs A, const int32_t* rows, int64_t m, const doubl
         const int64_t i = row_of(rows, j);
         const double cj = coef[j];
         for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes)
-            __hip_atomic_fetch_add(out + A.colidx[k], cj * widen(val[k]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(out + (int64_t)A.colidx[k] * stride, cj * widen(val[k]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 hipError_t launch_scatter(const MatArgs& A, const int32_t* rows, int64_t m, const double* coef, double* out,
-                          hipStream_t st) {
+                          int64_t stride, hipStream_t st) {
     const int blocks = grid_for(m * kRowLanes, 256);
     switch (A.val_dtype) {
-        case ASAGA_VAL_F64: k_scatter<double><<<blocks, 256, 0, st>>>(A, rows, m, coef, out); break;
-        case ASAGA_VAL_F32: k_scatter<float><<<blocks, 256, 0, st>>>(A, rows, m, coef, out); break;
-        case ASAGA_VAL_BF16: k_scatter<uint16_t><<<blocks, 256, 0, st>>>(A, rows, m, coef, out); break;
+        case ASAGA_VAL_F64: k_scatter<double><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride); break;
+        case ASAGA_VAL_F32: k_scatter<float><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride); break;
+        case ASAGA_VAL_BF16: k_scatter<uint16_t><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <typename XT>
-__global__ void k_axpy_x(const XT* x, int64_t d, double lambda, double* g) {
+__global__ void k_axpy_x(XView x, int64_t d, double lambda, double* g) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d; v += (int64_t)gridDim.x * blockDim.x)
-        g[v] += lambda * (double)x[v];
+        g[v] += lambda * xget(x, v);
 }
 
-hipError_t launch_axpy_x(const void* x, bool x_f32, int64_t d, double lambda, double* g, hipStream_t st) {
-    if (x_f32)
-        k_axpy_x<float><<<grid_for(d, 256), 256, 0, st>>>(static_cast<const float*>(x), d, lambda, g);
-    else
-        k_axpy_x<double><<<grid_for(d, 256), 256, 0, st>>>(static_cast<const double*>(x), d, lambda, g);
+hipError_t launch_axpy_x(XView x, int64_t d, double lambda, double* g, hipStream_t st) {
+    k_axpy_x<<<grid_for(d, 256), 256, 0, st>>>(x, d, lambda, g);
     return hipGetLastError();
 }
 
@@ -548,11 +775,11 @@ __device__ __forceinline__ double block_sum(double v) {
     return red[0];
 }
 
-template <typename T, bool SQUARE>
-__global__ void __launch_bounds__(256) k_sum_stage1(const T* in, int64_t count, double* part) {
+template <bool SQUARE>
+__global__ void __launch_bounds__(256) k_sum_stage1(XView x, int64_t count, double* part) {
     double s = 0.0, c = 0.0;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x) {
-        double v = (double)in[k];
+        double v = xget(x, k);
         if (SQUARE) v *= v;
         neumaier(s, c, v);
     }
@@ -565,21 +792,40 @@ __global__ void __launch_bounds__(kSumParts) k_sum_stage2(const double* part, do
     if (threadIdx.x == 0) *out = r;
 }
 
-template <typename T, bool SQUARE>
-static hipError_t launch_sum_t(const T* in, int64_t count, double* part, double* out, hipStream_t st) {
-    k_sum_stage1<T, SQUARE><<<kSumParts, 256, 0, st>>>(in, count, part);
+hipError_t launch_sum(const double* in, int64_t count, double* part, double* out, hipStream_t st) {
+    k_sum_stage1<false><<<kSumParts, 256, 0, st>>>(XView{in, 1, 0}, count, part);
     k_sum_stage2<<<1, kSumParts, 0, st>>>(part, out);
     return hipGetLastError();
 }
 
-hipError_t launch_sum(const double* in, int64_t count, bool square, double* part, double* out, hipStream_t st) {
-    return square ? launch_sum_t<double, true>(in, count, part, out, st)
-                  : launch_sum_t<double, false>(in, count, part, out, st);
+hipError_t launch_sum_x2(XView x, int64_t d, double* part, double* out, hipStream_t st) {
+    k_sum_stage1<true><<<kSumParts, 256, 0, st>>>(x, d, part);
+    k_sum_stage2<<<1, kSumParts, 0, st>>>(part, out);
+    return hipGetLastError();
 }
 
-hipError_t launch_sum_x2(const void* x, bool x_f32, int64_t d, double* part, double* out, hipStream_t st) {
-    return x_f32 ? launch_sum_t<float, true>(static_cast<const float*>(x), d, part, out, st)
-                 : launch_sum_t<double, true>(static_cast<const double*>(x), d, part, out, st);
+__global__ void k_gather_view(XView x, const int32_t* rank, int64_t d, double* out) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d; v += (int64_t)gridDim.x * blockDim.x)
+        out[v] = xget(x, rank[v]);
+}
+
+hipError_t launch_gather_view(XView x, const int32_t* rank, int64_t d, double* out, hipStream_t st) {
+    k_gather_view<<<grid_for(d, 256), 256, 0, st>>>(x, rank, d, out);
+    return hipGetLastError();
+}
+
+__global__ void k_scatter_slots(const double* in, const int32_t* rank, int64_t d, void* slot, int64_t stride, int f32) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = (int64_t)rank[v] * stride;
+        if (f32) static_cast<float*>(slot)[q] = (float)in[v];
+        else static_cast<double*>(slot)[q] = in[v];
+    }
+}
+
+hipError_t launch_scatter_slots(const double* in, const int32_t* rank, int64_t d, void* slot, int64_t stride, bool f32,
+                                hipStream_t st) {
+    k_scatter_slots<<<grid_for(d, 256), 256, 0, st>>>(in, rank, d, slot, stride, f32 ? 1 : 0);
+    return hipGetLastError();
 }
 
 __global__ void k_widen(const float* in, int64_t count, double* out) {

@@ -61,7 +61,8 @@ def good():
 def expect(code, **changes):
     kw = good()
     opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
-                                                              "waves", "step", "loss")}
+                                                              "waves", "step", "loss", "hot_columns",
+                                                              "flush_every")}
     kw.update(changes)
     with pytest.raises(A.AsagaError) as ei:
         A.Solver(**kw, **opts)
@@ -96,6 +97,9 @@ def test_bad_arguments_are_rejected():
     expect(E, waves=-1)
     expect(E, step=float("nan"))
     expect(E, loss=5)
+    expect(E, hot_columns=5000)
+    expect(E, hot_columns=-2)
+    expect(E, flush_every=-1)
     expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
 
 
