@@ -1,8 +1,9 @@
 """Benchmark of the asynchronous Sparse SAGA (ASAGA) hot path on one MI355X.
 
 Workload: the RCV1-shaped L2-logistic instance (700,000 x 47,000, ~75
-distinct Zipf(1.1) columns per row, lognormal values, rows L2-normalised,
-lambda = 1/n), plain FP64 asynchronous ASAGA.  One step = one epoch = n
+distinct Zipf(1.1) columns per row, TF-IDF-like values (lognormal term
+weight x smooth idf), rows L2-normalised, lambda = 1/n), plain FP64
+asynchronous ASAGA.  One step = one epoch = n
 sample updates of the whole hot path (sample, row fetch, gather and dot,
 scalar gradient, scatter of x and abar, memory update).
 
@@ -12,6 +13,11 @@ stream), the time to 1e-9 relative suboptimality from a cold start, and the
 CPU oracle timed on a bounded sample on this host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-tta]
+                    [--copy-calibration]
+
+--copy-calibration adds a plain 1 GiB device-to-device copy (known bytes
+read and written) so that a profiler's per-dispatch byte counters can be
+scaled to bytes in the same run.
 """
 from __future__ import annotations
 
@@ -71,6 +77,12 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle leg")
     ap.add_argument("--skip-tta", action="store_true", help="omit the time-to-accuracy leg")
     ap.add_argument("--cpu-epochs", type=int, default=20)
+    ap.add_argument("--hot", type=int, default=0)
+    ap.add_argument("--flush", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--step-scale", type=float, default=0.0,
+                    help="step as a multiple of the serial rule 1/(3L) (0: the library's asynchronous default)")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -102,14 +114,30 @@ def main():
     dev_arrays = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (p.rowptr, p.colidx, p.val, p.b)]
     torch.cuda.synchronize()
 
+    step = 0.0
+    if args.step_scale > 0:
+        step = args.step_scale / (3.0 * (0.25 * float(np.max(np.add.reduceat(p.val ** 2, p.rowptr[:-1]))) + p.lam))
+
     def make_solver():
-        return A.Solver(p.n, p.d, *dev_arrays, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC, seed=0,
-                        waves=args.waves, lanes_per_sample=args.lanes, stream=stream)
+        return A.Solver(p.n, p.d, *dev_arrays, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC, seed=0, step=step,
+                        waves=args.waves, lanes_per_sample=args.lanes, hot_columns=args.hot,
+                        flush_every=args.flush, threads_per_block=args.block, stream=stream)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {src.numel() * 8} bytes read and written")
+        del src, dst
 
     # ---- throughput: W warm-up epochs, then K timed epochs -------------------
     g = make_solver()
     info = g.info()
-    log(f"async: waves={info.waves} lanes/sample={info.lanes_per_sample} gamma={info.gamma:.6g} L={info.L:.6g}")
+    log(f"async: waves={info.waves} lanes/sample={info.lanes_per_sample} hot={info.hot_columns} "
+        f"flush={info.flush_every} block={info.threads_per_block} gamma={info.gamma:.6g} L={info.L:.6g}")
     for _ in range(args.warmup):
         g.epochs(1)
     torch.cuda.synchronize()
@@ -190,9 +218,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded RCV1-shaped stand-in; the paper's datasets are not available)",
         "config": {"workload": "config2: plain FP64 async ASAGA, L2 logistic, lambda=1/n, CSR 700000 x 47000, "
-                               "Poisson(75) Zipf(1.1) columns, lognormal values, rows L2-normalised",
+                               "Poisson(75) Zipf(1.1) columns, TF-IDF-like values, rows L2-normalised",
                    "n": p.n, "d": p.d, "nnz": p.nnz, "epochs_per_step": 1, "waves": info.waves,
-                   "lanes_per_sample": info.lanes_per_sample, "gamma": info.gamma},
+                   "lanes_per_sample": info.lanes_per_sample, "hot_columns": info.hot_columns,
+                   "flush_every": info.flush_every, "threads_per_block": info.threads_per_block,
+                   "gamma": info.gamma, "gamma_over_serial_rule": info.gamma * 3.0 * info.L},
         "hbm_gbps_algorithmic": achieved_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved_gbps / HBM_PEAK_GBPS, "traffic": traffic,

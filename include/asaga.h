@@ -35,11 +35,12 @@
  * Steele, Lea & Flood (2014) started from state `seed`.  One epoch = n samples.
  *
  * Step size: when opts.step <= 0, gamma = min(1/(3L), 1/(lambda max_v D_v))
- * with L = c max_i ||a_i||^2 + lambda, c = 1/4 (logistic) or 1 (squared).
- * With many samples in flight, updates read state that is older by up to
- * tau samples (Section 3.3, Assumption 1); the step must then shrink like
- * 1/tau along the directions many rows share (Theorem 2).  Async callers
- * pass a step chosen for their launch shape (see the autotuning notes).
+ * with L = c max_i ||a_i||^2 + lambda, c = 1/4 (logistic) or 1 (squared);
+ * in ASAGA_MODE_ASYNC that value is divided by 4.  With many samples in
+ * flight, updates read state that is older by up to tau samples (Section
+ * 3.3, Assumption 1), and the stable step shrinks as tau grows along the
+ * directions many rows share (Theorem 2); asaga_autotune measures the step
+ * and launch shape that reach a target accuracy soonest.
  *
  * Columns are relabelled internally by descending count; every vector that
  * crosses this interface (x, gradients, abar) is in the caller's order.
@@ -138,7 +139,8 @@ typedef struct asaga_opts {
     int32_t flush_every;      /* async: samples each lane group applies between
                                  two flushes of those combined writes
                                  (0 = automatic)                                  */
-    int32_t reserved;         /* must be 0 */
+    int32_t threads_per_block;/* async: workgroup size, a multiple of 64 up to
+                                 512 (0 = automatic)                              */
     void* stream;             /* hipStream_t */
 } asaga_opts;
 
@@ -170,7 +172,7 @@ typedef struct asaga_info {
     int32_t n_inst;
     int32_t hot_columns;
     int32_t flush_every;
-    int32_t reserved;
+    int32_t threads_per_block;
 } asaga_info;
 
 /* Create a context: validate the problem, copy host arrays to the device

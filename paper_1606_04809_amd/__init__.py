@@ -70,7 +70,7 @@ class asaga_opts(ctypes.Structure):
     _fields_ = [("step", ctypes.c_double), ("seed", ctypes.c_uint64), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("waves", ctypes.c_int32), ("lanes_per_sample", ctypes.c_int32),
                 ("racy", ctypes.c_int32), ("hot_columns", ctypes.c_int32), ("flush_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("threads_per_block", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class asaga_batch(ctypes.Structure):
@@ -83,7 +83,7 @@ class asaga_info(ctypes.Structure):
                 ("delta_r", ctypes.c_int64), ("t", ctypes.c_int64), ("L", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("lam", ctypes.c_double), ("waves", ctypes.c_int32),
                 ("lanes_per_sample", ctypes.c_int32), ("n_inst", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
-                ("flush_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flush_every", ctypes.c_int32), ("threads_per_block", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -249,7 +249,8 @@ class Solver:
 
     def __init__(self, n, d, rowptr, colidx, val, b, lam, loss=ASAGA_LOSS_LOGISTIC, val_dtype=None,
                  mode=ASAGA_MODE_SERIAL, precision=ASAGA_PREC_F64, step=0.0, seed=0, waves=0,
-                 lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, stream=None, batch=None):
+                 lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, threads_per_block=0, stream=None,
+                 batch=None):
         self.n, self.d = int(n), int(d)
         arrays = (rowptr, colidx, val, b)
         on_dev = [_is_torch_cuda(a) for a in arrays]
@@ -277,7 +278,7 @@ class Solver:
         if stream is not None and not isinstance(stream, int):
             stream = stream.cuda_stream
         self.opts = asaga_opts(float(step), int(seed), int(mode), int(precision), int(waves), int(lanes_per_sample),
-                               int(racy), int(hot_columns), int(flush_every), 0, stream)
+                               int(racy), int(hot_columns), int(flush_every), int(threads_per_block), stream)
         if batch is None:
             self.ctx = asaga_init(self.prob, self.opts)
             self.n_inst = 1

@@ -21,7 +21,9 @@ namespace {
 thread_local std::string g_init_error = "no error";
 
 constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
-constexpr int kMaxHot = 4096;  // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
+constexpr int kMaxHot = 4096;
+constexpr int kMaxBlock = 512;
+constexpr double kAsyncStepFactor = 0.25;  // the update kernels are compiled for at most 512 threads per workgroup  // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
 
 struct Inst {
     int64_t m = 0;
@@ -164,7 +166,8 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->hot_columns < -1 || o->hot_columns > kMaxHot)
         return fail(nullptr, ASAGA_E_ARG, "hot_columns must be -1, 0 or in [1, 4096]");
     if (o->flush_every < 0 || o->flush_every > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "flush_every out of range");
-    if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
+    if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
+        return fail(nullptr, ASAGA_E_ARG, "threads_per_block must be 0 or a multiple of 64 up to 512");
     return ASAGA_OK;
 }
 
@@ -266,6 +269,11 @@ int setup_instance(asaga_ctx* c, Inst& I) {
         const double dmax = stats[1] > 0 && stats[1] != 0x7fffffff ? (double)I.m / (double)stats[1] : 0.0;
         double g = 1.0 / (3.0 * I.L);
         if (I.lambda * dmax > 0.0 && 1.0 / (I.lambda * dmax) < g) g = 1.0 / (I.lambda * dmax);
+        // Asynchronous updates read state that is older by the number of
+        // samples in flight; the stable step shrinks with that delay
+        // (Theorem 2).  A quarter of the serial rule is the default for the
+        // default launch shape; asaga_autotune measures it per problem.
+        if (c->o.mode == ASAGA_MODE_ASYNC) g *= kAsyncStepFactor;
         I.gamma = g;
     }
     return zero_state(c, I);
@@ -293,12 +301,12 @@ void pick_shape(asaga_ctx* c) {
         lanes = p;
     }
     S.lanes = lanes;
-    S.block = 512;
+    S.block = c->o.threads_per_block > 0 ? c->o.threads_per_block : 512;
     int waves = c->o.waves;
     if (waves == 0) {
         int cus = device_cu_count();
         if (cus <= 0) cus = 256;
-        waves = cus * 16;
+        waves = cus * 8;
     }
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
@@ -306,7 +314,7 @@ void pick_shape(asaga_ctx* c) {
     if (hot == 0) hot = 2048;
     if (hot < 0 || S.racy) hot = 0;
     S.hot = (int)std::min<int64_t>(hot, c->d);
-    S.flush = c->o.flush_every > 0 ? c->o.flush_every : 4;
+    S.flush = c->o.flush_every > 0 ? c->o.flush_every : 1;
 }
 
 int free_all(asaga_ctx* c) {
@@ -698,7 +706,7 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->n_inst = (int32_t)c->inst.size();
     out->hot_columns = c->shape.hot;
     out->flush_every = c->shape.flush;
-    out->reserved = 0;
+    out->threads_per_block = c->shape.block;
     return ASAGA_OK;
 }
 

@@ -27,8 +27,8 @@
 //     are [0, H).  Each workgroup keeps them in LDS: a view of the global
 //     values and its own pending additions (LDS atomics run at ~1e12/s).
 //     Every F samples per group the workgroup adds its pending sums to the
-//     global state with line-coalesced atomics and refreshes the view from
-//     the values those atomics return.  Reads of hot columns touch only LDS;
+//     global state with line-coalesced atomics and refreshes the touched
+//     part of the view from the values those atomics return.  Reads of hot columns touch only LDS;
 //     this removes the per-line serialisation of the columns every row
 //     touches, and the L2 tag stalls of reading lines with atomics in
 //     flight (atomics execute at the memory side on MI355X).
@@ -292,27 +292,26 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
     if constexpr (SERIAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 
-// Add the workgroup's pending sums of the hot columns to the global state,
-// clear them, and refresh the view: a slot with a pending sum takes the value
-// its returning atomic add reports plus the sum, any other slot is read
-// again.  Consecutive threads take consecutive slots, so each wave
-// instruction covers 512 contiguous bytes (8 lines).
+// Add the workgroup's pending sums of the hot columns to the global state
+// and clear them.  A slot with a pending sum takes, as its new view, the
+// value its returning atomic add reports plus the sum (the global value
+// including every flush so far); untouched slots keep their view until the
+// workgroup next writes them.  Consecutive threads take consecutive slots,
+// so each wave instruction covers 512 contiguous bytes (8 lines).
 template <bool MIXED>
 __device__ __forceinline__ void flush_and_refresh(double* xa, int hot) {
     for (int q = threadIdx.x; q < 2 * hot; q += blockDim.x) {
         const double w = lds[2 * hot + q];
-        double now;
-        if (MIXED && (q & 1) == 0) {
-            float* p = reinterpret_cast<float*>(xa + q);
-            now = w != 0.0 ? (double)(__hip_atomic_fetch_add(p, (float)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                                      (float)w)
-                           : (double)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            now = w != 0.0 ? __hip_atomic_fetch_add(xa + q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + w
-                           : __hip_atomic_load(xa + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (w != 0.0) {
+            double now;
+            if (MIXED && (q & 1) == 0)
+                now = (double)(__hip_atomic_fetch_add(reinterpret_cast<float*>(xa + q), (float)w, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT) + (float)w);
+            else
+                now = __hip_atomic_fetch_add(xa + q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + w;
+            lds[q] = now;
+            lds[2 * hot + q] = 0.0;
         }
-        lds[q] = now;
-        lds[2 * hot + q] = 0.0;
     }
 }
 

@@ -62,7 +62,7 @@ def expect(code, **changes):
     kw = good()
     opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
                                                               "waves", "step", "loss", "hot_columns",
-                                                              "flush_every")}
+                                                              "flush_every", "threads_per_block")}
     kw.update(changes)
     with pytest.raises(A.AsagaError) as ei:
         A.Solver(**kw, **opts)
@@ -100,6 +100,9 @@ def test_bad_arguments_are_rejected():
     expect(E, hot_columns=5000)
     expect(E, hot_columns=-2)
     expect(E, flush_every=-1)
+    expect(E, threads_per_block=100)
+    expect(E, threads_per_block=2048)
+    expect(E, threads_per_block=1024)
     expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
 
 

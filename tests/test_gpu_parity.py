@@ -174,7 +174,8 @@ def test_async_small_reaches_optimum():
     assert r["converged"]
     sv = oracle.SparseSaga(p)
     for hot in (-1, 1024):
-        with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=64, hot_columns=hot, step=sv.gamma / 4) as g:
+        with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=64, hot_columns=hot) as g:
+            assert g.info().gamma == pytest.approx(sv.gamma / 4, rel=1e-14)
             for e in range(100):
                 g.epochs(5)
                 f = g.objective()
