@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--step-scale", type=float, default=0.0,
                     help="step as a multiple of the serial rule 1/(3L) (0: the library's asynchronous default)")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library's default launch shape and step instead of asaga_autotune's choice")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,10 +120,26 @@ def main():
     if args.step_scale > 0:
         step = args.step_scale / (3.0 * (0.25 * float(np.max(np.add.reduceat(p.val ** 2, p.rowptr[:-1]))) + p.lam))
 
+    shape = dict(waves=args.waves, lanes_per_sample=args.lanes, hot_columns=args.hot, flush_every=args.flush,
+                 threads_per_block=args.block)
+
     def make_solver():
         return A.Solver(p.n, p.d, *dev_arrays, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC, seed=0, step=step,
-                        waves=args.waves, lanes_per_sample=args.lanes, hot_columns=args.hot,
-                        flush_every=args.flush, threads_per_block=args.block, stream=stream)
+                        stream=stream, **shape)
+
+    # ---- autotuning (untimed): launch shape and step for time to 1e-9 ---------
+    tune = None
+    if not args.no_autotune:
+        t = time.time()
+        g = make_solver()
+        rep = g.autotune(target=1e-9, probe_epochs=9)
+        g.close()
+        tune = {"candidates": rep.candidates, "waves": rep.waves, "hot_columns": rep.hot_columns,
+                "hot_tier_columns": rep.hot_tier_columns, "gamma": rep.gamma, "ms_per_epoch": rep.ms_per_epoch,
+                "est_epochs": rep.est_epochs, "est_seconds": rep.est_seconds, "tuning_wall_s": time.time() - t}
+        log(f"autotune: {tune}")
+        step = rep.gamma
+        shape.update(waves=rep.waves, hot_columns=rep.hot_columns, hot_tier_columns=rep.hot_tier_columns)
 
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -229,6 +247,7 @@ def main():
                      "kernel": "k_update (async, FP64)", "bytes_per_update": bytes_per_update,
                      "launch_ms": avg_launch_s * 1e3},
         "time_to_1e-9": tta,
+        "autotune": tune,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -141,6 +141,11 @@ typedef struct asaga_opts {
                                  (0 = automatic)                                  */
     int32_t threads_per_block;/* async: workgroup size, a multiple of 64 up to
                                  512 (0 = automatic)                              */
+    int32_t hot_tier_columns; /* async: the first hot columns, flushed after every
+                                 round of flush_every samples; the others are
+                                 flushed every hot_tier_every rounds
+                                 (0 = automatic, -1 = all hot columns every round) */
+    int32_t hot_tier_every;   /* async: see hot_tier_columns (0 = automatic)      */
     void* stream;             /* hipStream_t */
 } asaga_opts;
 
@@ -173,7 +178,22 @@ typedef struct asaga_info {
     int32_t hot_columns;
     int32_t flush_every;
     int32_t threads_per_block;
+    int32_t hot_tier_columns;
+    int32_t hot_tier_every;
+    int32_t reserved;
 } asaga_info;
+
+/* What asaga_autotune measured and chose. */
+typedef struct asaga_tune_report {
+    int32_t candidates;       /* (launch shape, step) pairs probed                  */
+    int32_t waves;            /* chosen launch shape                                */
+    int32_t hot_columns;
+    int32_t hot_tier_columns;
+    double gamma;             /* chosen step                                        */
+    double ms_per_epoch;      /* measured kernel time per epoch at the choice       */
+    double est_epochs;        /* estimated epochs from a cold start to the target   */
+    double est_seconds;       /* estimated kernel seconds to the target             */
+} asaga_tune_report;
 
 /* Create a context: validate the problem, copy host arrays to the device
  * (device arrays are borrowed), count columns (D, Delta_r), compute L and
@@ -218,6 +238,19 @@ int asaga_set_state(asaga_ctx* ctx, int32_t inst, const double* x_host, const do
  * memory, removing the drift that concurrent or reduced-precision additions
  * leave in the running average (every instance). */
 int asaga_reanchor(asaga_ctx* ctx);
+
+/* Choose the asynchronous launch shape (wavefronts in flight, hot-set size
+ * and tier) and the step that reach relative suboptimality `target` soonest
+ * on this problem (single-instance async contexts).  For each candidate it
+ * times one epoch, then runs `probe_epochs` epochs from x = 0 for each step
+ * of a ladder (1/2 .. 1/16 of the serial rule), measures the decay rate of
+ * ||grad f|| (FP64 full gradients at three checkpoints; a candidate whose
+ * gradient norm does not decrease at every checkpoint is rejected as
+ * unstable), and extrapolates to ||grad f||^2 <= 2 lambda target f, which
+ * bounds (f - f*)/f by `target` (f is lambda-strongly convex).  The best
+ * candidate is kept, the state is reset to x = alpha = abar = 0, t = 0.
+ * Returns ASAGA_E_DIVERGED if no candidate was stable. */
+int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);
 
 /* Derived numbers (instance 0, plus launch shape). */
 int asaga_info_get(asaga_ctx* ctx, asaga_info* out);

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libasaga.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
-                      "(python -m paper_1606_04809_amd.build, or __graft_entry__.build())")
+                      "(python paper_1606_04809_amd/build.py, or __graft_entry__.build())")
 
 # One HIP runtime per process: torch ships its own libamdhip64 (same SONAME
 # as the system one).  Loading torch first lets the dynamic loader resolve
@@ -70,7 +70,8 @@ class asaga_opts(ctypes.Structure):
     _fields_ = [("step", ctypes.c_double), ("seed", ctypes.c_uint64), ("mode", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("waves", ctypes.c_int32), ("lanes_per_sample", ctypes.c_int32),
                 ("racy", ctypes.c_int32), ("hot_columns", ctypes.c_int32), ("flush_every", ctypes.c_int32),
-                ("threads_per_block", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("threads_per_block", ctypes.c_int32), ("hot_tier_columns", ctypes.c_int32),
+                ("hot_tier_every", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class asaga_batch(ctypes.Structure):
@@ -78,12 +79,20 @@ class asaga_batch(ctypes.Structure):
                 ("inst_fold", ctypes.c_void_p), ("inst_lambda", ctypes.c_void_p)]
 
 
+class asaga_tune_report(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("waves", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
+                ("hot_tier_columns", ctypes.c_int32), ("gamma", ctypes.c_double), ("ms_per_epoch", ctypes.c_double),
+                ("est_epochs", ctypes.c_double), ("est_seconds", ctypes.c_double)]
+
+
 class asaga_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("delta_r", ctypes.c_int64), ("t", ctypes.c_int64), ("L", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("lam", ctypes.c_double), ("waves", ctypes.c_int32),
                 ("lanes_per_sample", ctypes.c_int32), ("n_inst", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
-                ("flush_every", ctypes.c_int32), ("threads_per_block", ctypes.c_int32)]
+                ("flush_every", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
+                ("hot_tier_columns", ctypes.c_int32), ("hot_tier_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -100,6 +109,7 @@ _SIGS = {
     "asaga_get_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "asaga_set_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "asaga_reanchor": (ctypes.c_int, [_CTX]),
+    "asaga_autotune": (ctypes.c_int, [_CTX, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(asaga_tune_report)]),
     "asaga_info_get": (ctypes.c_int, [_CTX, ctypes.POINTER(asaga_info)]),
     "asaga_sync": (ctypes.c_int, [_CTX]),
     "asaga_sample_stream": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
@@ -207,6 +217,12 @@ def asaga_reanchor(ctx):
     return _check(_lib.asaga_reanchor(ctx), ctx)
 
 
+def asaga_autotune(ctx, target: float = 1e-9, probe_epochs: int = 9) -> asaga_tune_report:
+    rep = asaga_tune_report()
+    _check(_lib.asaga_autotune(ctx, float(target), int(probe_epochs), ctypes.byref(rep)), ctx)
+    return rep
+
+
 def asaga_info_get(ctx) -> asaga_info:
     info = asaga_info()
     _check(_lib.asaga_info_get(ctx, ctypes.byref(info)), ctx)
@@ -249,8 +265,8 @@ class Solver:
 
     def __init__(self, n, d, rowptr, colidx, val, b, lam, loss=ASAGA_LOSS_LOGISTIC, val_dtype=None,
                  mode=ASAGA_MODE_SERIAL, precision=ASAGA_PREC_F64, step=0.0, seed=0, waves=0,
-                 lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, threads_per_block=0, stream=None,
-                 batch=None):
+                 lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, threads_per_block=0,
+                 hot_tier_columns=0, hot_tier_every=0, stream=None, batch=None):
         self.n, self.d = int(n), int(d)
         arrays = (rowptr, colidx, val, b)
         on_dev = [_is_torch_cuda(a) for a in arrays]
@@ -278,7 +294,8 @@ class Solver:
         if stream is not None and not isinstance(stream, int):
             stream = stream.cuda_stream
         self.opts = asaga_opts(float(step), int(seed), int(mode), int(precision), int(waves), int(lanes_per_sample),
-                               int(racy), int(hot_columns), int(flush_every), int(threads_per_block), stream)
+                               int(racy), int(hot_columns), int(flush_every), int(threads_per_block),
+                               int(hot_tier_columns), int(hot_tier_every), stream)
         if batch is None:
             self.ctx = asaga_init(self.prob, self.opts)
             self.n_inst = 1
@@ -316,6 +333,9 @@ class Solver:
 
     def reanchor(self):
         asaga_reanchor(self.ctx)
+
+    def autotune(self, target: float = 1e-9, probe_epochs: int = 9) -> asaga_tune_report:
+        return asaga_autotune(self.ctx, target, probe_epochs)
 
     def info(self) -> asaga_info:
         return asaga_info_get(self.ctx)

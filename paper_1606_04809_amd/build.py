@@ -1,7 +1,9 @@
 """Build step of the HIP library: compiles csrc/*.hip for gfx950 into
 libasaga.so next to this file (in the source tree, so that it travels with it).
 
-    python -m paper_1606_04809_amd.build
+    python paper_1606_04809_amd/build.py
+
+(Run it as a script: importing the package would load the library first.)
 """
 from __future__ import annotations
 

@@ -166,6 +166,10 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->hot_columns < -1 || o->hot_columns > kMaxHot)
         return fail(nullptr, ASAGA_E_ARG, "hot_columns must be -1, 0 or in [1, 4096]");
     if (o->flush_every < 0 || o->flush_every > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "flush_every out of range");
+    if (o->hot_tier_columns < -1 || o->hot_tier_columns > kMaxHot)
+        return fail(nullptr, ASAGA_E_ARG, "hot_tier_columns must be -1, 0 or in [1, 4096]");
+    if (o->hot_tier_every < 0 || o->hot_tier_every > (1 << 16))
+        return fail(nullptr, ASAGA_E_ARG, "hot_tier_every out of range");
     if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
         return fail(nullptr, ASAGA_E_ARG, "threads_per_block must be 0 or a multiple of 64 up to 512");
     return ASAGA_OK;
@@ -290,6 +294,8 @@ void pick_shape(asaga_ctx* c) {
         S.block = 64;
         S.hot = 0;
         S.flush = 1;
+        S.tier = 0;
+        S.tier_every = 1;
         return;
     }
     const double mean = (double)c->nnz / (double)c->n;
@@ -311,10 +317,15 @@ void pick_shape(asaga_ctx* c) {
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
     int hot = c->o.hot_columns;
-    if (hot == 0) hot = 2048;
+    if (hot == 0) hot = 4096;
     if (hot < 0 || S.racy) hot = 0;
     S.hot = (int)std::min<int64_t>(hot, c->d);
     S.flush = c->o.flush_every > 0 ? c->o.flush_every : 1;
+    // first tier: the 256 most-used columns, flushed every round; the rest of
+    // the hot set every 16 rounds
+    const int tier = c->o.hot_tier_columns == 0 ? 256 : c->o.hot_tier_columns < 0 ? S.hot : c->o.hot_tier_columns;
+    S.tier = std::min(tier, S.hot);
+    S.tier_every = c->o.hot_tier_every > 0 ? c->o.hot_tier_every : 16;
 }
 
 int free_all(asaga_ctx* c) {
@@ -689,6 +700,149 @@ int asaga_reanchor(asaga_ctx* c) {
     return ASAGA_OK;
 }
 
+namespace {
+
+// ||grad f(x)||^2 and f(x) at instance 0's current iterate (FP64)
+int grad_norm2(asaga_ctx* c, double* g2, double* f) {
+    const Inst& I = c->inst[0];
+    const XView x = x_view(c, I);
+    const MatArgs A = mat(c);
+    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, c->z, c->st));
+    HIPCHK(c, launch_phi_terms(A, I.rows, I.m, c->z, c->tmp, c->st));
+    HIPCHK(c, launch_sum(c->tmp, I.m, c->part, c->scal + 0, c->st));
+    HIPCHK(c, launch_sum_x2(x, c->d, c->part, c->scal + 1, c->st));
+    HIPCHK(c, launch_dphi_coef(A, I.rows, I.m, c->z, 1.0 / (double)I.m, c->tmp, c->st));
+    HIPCHK(c, launch_fill_f64(c->vec2, 0.0, c->d, 1, c->st));
+    HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, c->vec2, 1, c->st));
+    HIPCHK(c, launch_axpy_x(x, c->d, I.lambda, c->vec2, c->st));
+    HIPCHK(c, launch_sum_x2(XView{c->vec2, 1, 0}, c->d, c->part, c->scal + 2, c->st));
+    double s[3];
+    HIPCHK(c, hipMemcpyAsync(s, c->scal, sizeof(s), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    *f = s[0] / (double)I.m + 0.5 * I.lambda * s[1];
+    *g2 = s[2];
+    return ASAGA_OK;
+}
+
+int reset_state(asaga_ctx* c) {
+    for (auto& I : c->inst) {
+        int rc = zero_state(c, I);
+        if (rc) return rc;
+    }
+    HIPCHK(c, launch_fill_i32(c->flag, 0, 1, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    return ASAGA_OK;
+}
+
+}  // namespace
+
+int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune_report* rep) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (c->d_insts || c->shape.serial) return fail(c, ASAGA_E_STATE, "autotuning needs a single-instance async context");
+    if (!(target > 0.0 && target < 1.0)) return fail(c, ASAGA_E_ARG, "target must be in (0, 1)");
+    if (probe_epochs < 3 || probe_epochs > 1000) return fail(c, ASAGA_E_ARG, "probe_epochs must be in [3, 1000]");
+    Inst& I = c->inst[0];
+    const UpdateShape base = c->shape;
+    const double serial_rule = c->o.step > 0.0 ? c->o.step : I.gamma / kAsyncStepFactor;
+    int cus = device_cu_count();
+    if (cus <= 0) cus = 256;
+    const int wpb = base.block / 64;
+    auto round_waves = [&](int w) { return std::max(wpb, ((w + wpb - 1) / wpb) * wpb); };
+    std::vector<UpdateShape> shapes;
+    for (int w : {cus * 4, cus * 8})
+        for (int h : {1024, 4096}) {
+            UpdateShape S = base;
+            S.waves = round_waves(w);
+            S.hot = (int)std::min<int64_t>(h, c->d);
+            S.tier = std::min(256, S.hot);
+            S.tier_every = 16;
+            shapes.push_back(S);
+        }
+    const double scales[] = {0.5, 0.25, 0.125, 0.0625};
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    struct Best {
+        double est_s = INFINITY, est_e = 0, ms = 0, gamma = 0;
+        UpdateShape S{};
+    } best;
+    int tried = 0, rc = ASAGA_OK;
+    const int cps[3] = {probe_epochs / 3, 2 * probe_epochs / 3, probe_epochs};
+    for (const UpdateShape& S : shapes) {
+        c->shape = S;
+        // kernel time per epoch at this shape
+        if ((rc = reset_state(c))) break;
+        hipError_t he = hipEventRecord(e0, c->st);
+        if (he == hipSuccess && (rc = asaga_updates(c, I.m)) != ASAGA_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, c->st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) {
+            rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
+        for (double sc : scales) {
+            ++tried;
+            I.gamma = serial_rule * sc;
+            if ((rc = reset_state(c))) break;
+            double g2[3], f[3];
+            int done = 0;
+            bool ok = true;
+            for (int k = 0; k < 3 && ok; ++k) {
+                if ((rc = asaga_updates(c, (int64_t)(cps[k] - done) * I.m))) break;
+                done = cps[k];
+                if ((rc = grad_norm2(c, &g2[k], &f[k]))) break;
+                ok = std::isfinite(g2[k]) && std::isfinite(f[k]) && (k == 0 || g2[k] < g2[k - 1]);
+            }
+            if (rc) break;
+            int flag = 0;
+            HIPCHK(c, hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+            if (!ok || flag) continue;
+            // ||g|| decays like exp(-r t): r per epoch from the last two checkpoints
+            const double r = 0.5 * std::log(g2[1] / g2[2]) / (double)(cps[2] - cps[1]);
+            const double goal = 2.0 * I.lambda * target * f[2];
+            const double more = g2[2] > goal ? 0.5 * std::log(g2[2] / goal) / r : 0.0;
+            const double est_e = (double)cps[2] + more;
+            const double est_s = est_e * (double)ms * 1e-3;
+            if (est_s < best.est_s) {
+                best.est_s = est_s;
+                best.est_e = est_e;
+                best.ms = ms;
+                best.gamma = I.gamma;
+                best.S = S;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        c->shape = base;
+        return rc;
+    }
+    if (!std::isfinite(best.est_s)) {
+        c->shape = base;
+        I.gamma = serial_rule * kAsyncStepFactor;
+        reset_state(c);
+        return fail(c, ASAGA_E_DIVERGED, "no probed launch shape and step reduced the gradient norm steadily");
+    }
+    c->shape = best.S;
+    I.gamma = best.gamma;
+    if ((rc = reset_state(c))) return rc;
+    if (rep) {
+        rep->candidates = tried;
+        rep->waves = best.S.waves;
+        rep->hot_columns = best.S.hot;
+        rep->hot_tier_columns = best.S.tier;
+        rep->gamma = best.gamma;
+        rep->ms_per_epoch = best.ms;
+        rep->est_epochs = best.est_e;
+        rep->est_seconds = best.est_s;
+    }
+    return ASAGA_OK;
+}
+
 int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
     if (!out) return fail(c, ASAGA_E_ARG, "NULL info");
@@ -707,6 +861,9 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->hot_columns = c->shape.hot;
     out->flush_every = c->shape.flush;
     out->threads_per_block = c->shape.block;
+    out->hot_tier_columns = c->shape.tier;
+    out->hot_tier_every = c->shape.tier_every;
+    out->reserved = 0;
     return ASAGA_OK;
 }
 

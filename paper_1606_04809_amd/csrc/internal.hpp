@@ -41,6 +41,11 @@ struct MatArgs {
     int32_t loss;        // ASAGA_LOSS_*
 };
 
+// Hot-set parameters the update kernels receive.
+struct HotArgs {
+    int hot, flush, tier, tier_every;
+};
+
 // launch shape and variant of the Sparse SAGA update kernel
 struct UpdateShape {
     int lanes;        // lanes per sample: 64, 32, 16 or 8
@@ -48,6 +53,8 @@ struct UpdateShape {
     int block;        // threads per workgroup
     int hot;          // columns [0, hot) combined in LDS per workgroup (0: none)
     int flush;        // samples per lane group between flushes of the LDS buffer
+    int tier;         // columns [0, tier) flush every round, [tier, hot) every tier_every rounds
+    int tier_every;
     bool serial;      // one wave, ordered: agent-scope fence between updates
     bool racy;        // plain read-modify-write (negative control)
     bool mixed;       // FP32 x and alpha

@@ -28,7 +28,9 @@
 //     values and its own pending additions (LDS atomics run at ~1e12/s).
 //     Every F samples per group the workgroup adds its pending sums to the
 //     global state with line-coalesced atomics and refreshes the touched
-//     part of the view from the values those atomics return.  Reads of hot columns touch only LDS;
+//     part of the view from the values those atomics return; the first tier
+//     of hot columns (those nearly every row touches) is flushed every
+//     round, the rest of the hot set every few rounds.  Reads of hot columns touch only LDS;
 //     this removes the per-line serialisation of the columns every row
 //     touches, and the L2 tag stalls of reading lines with atomics in
 //     flight (atomics execute at the memory side on MI355X).
@@ -292,15 +294,15 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
     if constexpr (SERIAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 
-// Add the workgroup's pending sums of the hot columns to the global state
-// and clear them.  A slot with a pending sum takes, as its new view, the
+// Add the workgroup's pending sums of hot columns [0, upto) to the global
+// state and clear them.  A slot with a pending sum takes, as its new view, the
 // value its returning atomic add reports plus the sum (the global value
 // including every flush so far); untouched slots keep their view until the
 // workgroup next writes them.  Consecutive threads take consecutive slots,
 // so each wave instruction covers 512 contiguous bytes (8 lines).
 template <bool MIXED>
-__device__ __forceinline__ void flush_and_refresh(double* xa, int hot) {
-    for (int q = threadIdx.x; q < 2 * hot; q += blockDim.x) {
+__device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto) {
+    for (int q = threadIdx.x; q < 2 * upto; q += blockDim.x) {
         const double w = lds[2 * hot + q];
         if (w != 0.0) {
             double now;
@@ -333,20 +335,24 @@ __device__ __forceinline__ void load_view(const double* xa, int hot) {
 // groups: group `slot` applies samples s = slot + k * slots, k = 0, 1, ...
 // The row bounds of the next sample are fetched while the current one is
 // processed.  With a hot set, all groups of the workgroup advance in rounds
-// of `flush` samples and the workgroup flushes its LDS sums after each round.
+// of `flush` samples; after each round the workgroup flushes the first
+// `tier` hot columns, and all hot columns every `tier_every` rounds and at
+// the end of the launch.
 template <int G, int P, bool SERIAL, bool RACY, bool MIXED, typename VT>
 __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, uint64_t t0, uint64_t slot,
-                                          uint64_t slots, int hot, int flush, int* flag) {
+                                          uint64_t slots, HotArgs H, int* flag) {
     const int gl = threadIdx.x & (G - 1);
+    const int hot = H.hot;
     const uint64_t kmax = (I.count + slots - 1) / slots;
     if (hot > 0) {
         load_view<MIXED>(I.xa, hot);
         __syncthreads();
     }
-    const uint64_t round = hot > 0 ? (uint64_t)flush : kmax;
+    const uint64_t round = hot > 0 ? (uint64_t)H.flush : kmax;
     RowRef cur{0, 0, 0, 0, 0.0, 0.0};
     if (slot < I.count) cur = row_ref<SERIAL, MIXED>(A, I, t0 + slot);
-    for (uint64_t k0 = 0; k0 < kmax; k0 += round) {
+    uint64_t r = 0;
+    for (uint64_t k0 = 0; k0 < kmax; k0 += round, ++r) {
         const uint64_t k1 = k0 + round < kmax ? k0 + round : kmax;
         for (uint64_t k = k0; k < k1; ++k) {
             const uint64_t s = slot + k * slots;
@@ -357,8 +363,9 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
             cur = nxt;
         }
         if (hot > 0) {
+            const bool all = k1 == kmax || (r + 1) % (uint64_t)H.tier_every == 0;
             __syncthreads();
-            flush_and_refresh<MIXED>(I.xa, hot);
+            flush_and_refresh<MIXED>(I.xa, hot, all ? hot : H.tier);
             __syncthreads();
         }
     }
@@ -368,26 +375,25 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
 constexpr int kPasses = 4;
 
 template <int G, bool SERIAL, bool RACY, bool MIXED, typename VT>
-__global__ void __launch_bounds__(512) k_update(MatArgs A, InstArgs I, int hot, int flush, int* flag) {
+__global__ void __launch_bounds__(512) k_update(MatArgs A, InstArgs I, HotArgs H, int* flag) {
     const uint64_t groups = blockDim.x / G;
     const uint64_t slot = blockIdx.x * groups + threadIdx.x / G;
     const uint64_t slots = (uint64_t)gridDim.x * groups;
-    run_slots<G, kPasses, SERIAL, RACY, MIXED, VT>(A, I, I.t0, slot, slots, hot, flush, flag);
+    run_slots<G, kPasses, SERIAL, RACY, MIXED, VT>(A, I, I.t0, slot, slots, H, flag);
 }
 
 // Many instances in one persistent grid: blocks_per_inst consecutive
 // workgroups serve one instance.
 template <int G, bool MIXED, typename VT>
 __global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArgs* insts, int n_inst,
-                                                        int blocks_per_inst, uint64_t epoch, int hot, int flush,
-                                                        int* flag) {
+                                                        int blocks_per_inst, uint64_t epoch, HotArgs H, int* flag) {
     const int inst = (int)(blockIdx.x / (unsigned)blocks_per_inst);
     if (inst >= n_inst) return;
     const InstArgs I = insts[inst];
     const uint64_t groups = blockDim.x / G;
     const uint64_t slot = (blockIdx.x % (unsigned)blocks_per_inst) * groups + threadIdx.x / G;
     const uint64_t slots = (uint64_t)blocks_per_inst * groups;
-    run_slots<G, kPasses, false, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, hot, flush, flag);
+    run_slots<G, kPasses, false, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, H, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,12 +402,21 @@ __global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArg
 
 size_t update_lds_bytes(const UpdateShape& S) { return (size_t)S.hot * 4 * sizeof(double); }
 
+static HotArgs hot_args(const UpdateShape& S) {
+    HotArgs H;
+    H.hot = S.hot;
+    H.flush = S.flush > 0 ? S.flush : 1;
+    H.tier = S.tier > 0 && S.tier < S.hot ? S.tier : S.hot;
+    H.tier_every = S.tier_every > 0 ? S.tier_every : 1;
+    return H;
+}
+
 template <bool MIXED, typename VT>
 static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag,
                                    hipStream_t st) {
     if (I.count == 0) return hipSuccess;
     if (S.serial) {
-        k_update<64, true, false, MIXED, VT><<<1, 64, 0, st>>>(A, I, 0, 1, flag);
+        k_update<64, true, false, MIXED, VT><<<1, 64, 0, st>>>(A, I, HotArgs{0, 1, 0, 1}, flag);
         return hipGetLastError();
     }
     const int threads = S.block;
@@ -410,7 +425,7 @@ static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const Up
 #define ASAGA_LAUNCH(GG)                                                                                     \
     case GG:                                                                                                 \
         if (S.racy) {                                                                                        \
-            k_update<GG, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, 0, 1, flag);             \
+            k_update<GG, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, HotArgs{0, 1, 0, 1}, flag); \
         } else {                                                                                             \
             if (lds > 65536) {                                                                               \
                 const hipError_t e = hipFuncSetAttribute(                                                    \
@@ -418,7 +433,7 @@ static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const Up
                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                                   \
                 if (e != hipSuccess) return e;                                                               \
             }                                                                                                \
-            k_update<GG, false, false, MIXED, VT><<<blocks, threads, lds, st>>>(A, I, S.hot, S.flush, flag); \
+            k_update<GG, false, false, MIXED, VT><<<blocks, threads, lds, st>>>(A, I, hot_args(S), flag);   \
         }                                                                                                    \
         break;
     switch (S.lanes) {
@@ -459,7 +474,7 @@ static hipError_t launch_batched_g(const MatArgs& A, const InstArgs* insts, int 
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_update_batched<G, MIXED, VT><<<blocks, threads, lds, st>>>(A, insts, n_inst, bpi, epoch, S.hot, S.flush, flag);
+    k_update_batched<G, MIXED, VT><<<blocks, threads, lds, st>>>(A, insts, n_inst, bpi, epoch, hot_args(S), flag);
     return hipGetLastError();
 }
 

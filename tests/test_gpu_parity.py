@@ -195,7 +195,7 @@ def test_async_config2_full_reaches_1e9(golden):
     fstar = golden["config2"]["f_lower"]
     with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC) as g:
         info = g.info()
-        say(f"config2 async: waves {info.waves} lanes {info.lanes_per_sample} gamma {info.gamma}")
+        say(f"config2 async: waves {info.waves} lanes {info.lanes_per_sample} hot {info.hot_columns} gamma {info.gamma}")
         hist = []
         for e in range(60):
             g.epochs(1)
@@ -205,3 +205,91 @@ def test_async_config2_full_reaches_1e9(golden):
                 break
         say(f"config2 async: epochs {len(hist)} rel {hist[-1]:.3e}")
         assert hist[-1] <= 1e-9
+        x, alpha, abar, t = g.get_state()
+        assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-11
+
+
+def test_autotune_picks_a_stable_shape_and_converges():
+    p = datagen.config2(n=30_000, d=6000)
+    r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC) as g:
+        rep = g.autotune(target=1e-9, probe_epochs=9)
+        say(f"autotune: {rep.candidates} candidates, waves {rep.waves} hot {rep.hot_columns} gamma {rep.gamma:.4g} "
+            f"{rep.ms_per_epoch:.3f} ms/epoch, est {rep.est_epochs:.1f} epochs / {rep.est_seconds:.4f} s")
+        assert rep.candidates >= 4 and rep.gamma > 0 and rep.est_epochs >= 9
+        info = g.info()
+        assert info.t == 0 and info.gamma == rep.gamma and info.waves == rep.waves
+        assert np.all(g.get_x() == 0.0)
+        for e in range(40):
+            g.epochs(5)
+            rel = (g.objective() - r["f_lower"]) / r["f_lower"]
+            if rel <= 1e-9:
+                break
+        say(f"autotuned run: {5 * (e + 1)} epochs, rel {rel:.2e}")
+        assert rel <= 1e-9
+
+
+def test_batched_instances_reach_their_own_optimum():
+    p = datagen.config2(n=12_000, d=3000)
+    row_fold = datagen.folds5(p.n, seed=0)
+    lams = np.array([1e-4, 1e-3])
+    folds = [0, 3]
+    inst_fold = np.array([f for f in folds for _ in lams], dtype=np.int32)
+    inst_lam = np.array([l for _ in folds for l in lams])
+    fstars = []
+    for f, lam in zip(inst_fold, inst_lam):
+        sub = datagen.subproblem(p, np.nonzero(row_fold != f)[0], lam=lam)
+        fstars.append(oracle.certified_fstar(sub, tol=1e-12, check_every=10)["f_lower"])
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=64, batch=(row_fold, inst_fold, inst_lam)) as g:
+        assert g.info().n_inst == 4
+        for e in range(60):
+            g.epochs(5)
+            rels = [(g.objective(k) - fs) / fs for k, fs in enumerate(fstars)]
+            if max(rels) <= 1e-9:
+                break
+        say(f"batched: {5 * (e + 1)} epochs, rel {['%.1e' % r for r in rels]}")
+        assert max(rels) <= 1e-9
+        # each instance's abar is the running average of its own memory
+        for k, (f, lam) in enumerate(zip(inst_fold, inst_lam)):
+            rows = np.nonzero(row_fold != f)[0]
+            sub = datagen.subproblem(p, rows, lam=lam)
+            x, alpha, abar, t = g.get_state(k, m=len(rows))
+            assert t == 5 * (e + 1) * len(rows)
+            assert rel_err(abar, oracle.SparseSaga(sub).memory_average(alpha)) < 1e-11
+
+
+def test_mixed_precision_reaches_1e9():
+    p = datagen.config2(n=20_000, d=5000)
+    r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED, waves=64) as g:
+        for e in range(60):
+            g.epochs(5)
+            rel = (g.objective() - r["f_lower"]) / r["f_lower"]
+            if rel <= 1e-9:
+                break
+        say(f"mixed FP32 x/alpha, FP64 abar: {5 * (e + 1)} epochs, rel {rel:.2e}")
+        assert rel <= 1e-9
+        x, alpha, abar, t = g.get_state()
+        # FP32 memory: alpha_i + delta rounds to FP32 whenever another wavefront
+        # changed alpha_i between this sample's read and write (a few percent of
+        # updates on 20,000 rows), while abar receives delta in FP64; the
+        # running average therefore agrees to FP32 rounding, not FP64
+        err = rel_err(abar, oracle.SparseSaga(p).memory_average(alpha))
+        say(f"mixed: abar vs (1/n) A^T alpha: {err:.1e}")
+        assert err < 1e-6
+
+
+def test_racy_updates_lose_information():
+    # Appendix G: without atomic additions concurrent updates overwrite each
+    # other; the lost abar increments show up as a broken running average
+    p = datagen.config2(n=20_000, d=2000)
+    sv = oracle.SparseSaga(p)
+    errs = {}
+    for racy in (0, 1):
+        with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=1024, racy=racy, hot_columns=-1) as g:
+            g.epochs(5)
+            x, alpha, abar, t = g.get_state()
+            errs[racy] = rel_err(abar, sv.memory_average(alpha))
+    say(f"invariant error: atomic {errs[0]:.1e}, racy {errs[1]:.1e}")
+    assert errs[0] < 1e-11
+    assert errs[1] > 1e-6
