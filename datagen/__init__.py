@@ -21,7 +21,8 @@ available, so each generator stands in for one of them with the same shape
   Zipf(1.2) columns, binary values row-normalised and stored as bfloat16,
   planted labels with 5% flips.
 * ``folds5`` / ``lambda_grid5``  the cross-validation folds and regularisation
-  path laid over the config-2 matrix for batched solves.
+  path laid over the config-2 matrix for batched solves; ``config5`` puts
+  them together over the bfloat16-stored config-2 matrix (160 instances).
 
 Every random draw comes from ``numpy.random.default_rng`` seeded by
 ``SeedSequence([seed, tag])`` with one tag per independent sub-stream, plus a
@@ -267,6 +268,46 @@ def subproblem(p: Problem, rows: np.ndarray, lam: float | None = None, name: str
     bits = p.val_bf16[gather] if p.val_bf16 is not None else None
     return Problem(name or p.name + "_sub", len(rows), p.d, rowptr, p.colidx[gather], p.val[gather],
                    p.b[rows], p.loss, p.lam if lam is None else lam, val_bf16=bits, meta=dict(p.meta))
+
+
+@dataclass
+class Batch:
+    """Many solves over one shared matrix: instance k trains on the rows
+    whose fold differs from ``inst_fold[k]`` (all rows if it is -1), with
+    regularisation ``inst_lambda[k]``."""
+    problem: Problem
+    row_fold: np.ndarray      # int8 [n]
+    inst_fold: np.ndarray     # int32 [n_inst]
+    inst_lambda: np.ndarray   # float64 [n_inst]
+
+    @property
+    def n_inst(self) -> int:
+        return len(self.inst_fold)
+
+    def rows(self, k: int) -> np.ndarray:
+        f = int(self.inst_fold[k])
+        return np.arange(self.problem.n) if f < 0 else np.nonzero(self.row_fold != f)[0]
+
+    def instance(self, k: int) -> Problem:
+        """Instance k as a problem of its own (its training rows in matrix order)."""
+        return subproblem(self.problem, self.rows(k), lam=float(self.inst_lambda[k]),
+                          name=f"{self.problem.name}[{k}]")
+
+
+def config5(seed: int = 0, n: int = 700_000, d: int = 47_000, n_lambda: int = 32, **kw) -> Batch:
+    """The config-2 matrix with its values stored as bfloat16 (the quantised
+    matrix is the instance, ``val`` its exact float64 widening; labels are
+    config 2's), five uneven folds and a 32-value lambda path over
+    1e-8..1e-2: 160 instances, lambda-major (instance k = lambda index k // 5,
+    fold k % 5)."""
+    p = config2(seed=seed, n=n, d=d, **kw)
+    bits = bf16_round(p.val)
+    q = Problem("config5", p.n, p.d, p.rowptr, p.colidx, bf16_widen(bits), p.b, p.loss, p.lam, val_bf16=bits,
+                meta=dict(p.meta))
+    lams = lambda_grid5(n_lambda)
+    inst_fold = np.tile(np.arange(5, dtype=np.int32), n_lambda)
+    inst_lambda = np.repeat(lams, 5)
+    return Batch(q, folds5(p.n, seed), inst_fold, inst_lambda)
 
 
 def by_name(name: str, **kw) -> Problem:

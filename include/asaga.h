@@ -239,17 +239,22 @@ int asaga_set_state(asaga_ctx* ctx, int32_t inst, const double* x_host, const do
  * leave in the running average (every instance). */
 int asaga_reanchor(asaga_ctx* ctx);
 
-/* Choose the asynchronous launch shape (wavefronts in flight, hot-set size
- * and tier) and the step that reach relative suboptimality `target` soonest
- * on this problem (single-instance async contexts).  For each candidate it
- * times one epoch, then runs `probe_epochs` epochs from x = 0 for each step
- * of a ladder (1/2 .. 1/16 of the serial rule), measures the decay rate of
- * ||grad f|| (FP64 full gradients at three checkpoints; a candidate whose
- * gradient norm does not decrease at every checkpoint is rejected as
- * unstable), and extrapolates to ||grad f||^2 <= 2 lambda target f, which
- * bounds (f - f*)/f by `target` (f is lambda-strongly convex).  The best
- * candidate is kept, the state is reset to x = alpha = abar = 0, t = 0.
- * Returns ASAGA_E_DIVERGED if no candidate was stable. */
+/* Choose the number of wavefronts in flight and the step that reach
+ * relative suboptimality `target` soonest on this problem (single-instance
+ * async contexts; the other shape parameters stay as the context has them).
+ * Fewer samples in flight tolerate a larger step (Theorem 2) but take longer
+ * per epoch, so wavefront counts are tried from 8 per compute unit down to
+ * 1/8 per compute unit, halving.  For each count it times one epoch, then,
+ * for steps from the serial rule downwards by halves (to 1/64 of it), runs
+ * `probe_epochs` epochs from x = 0, measures the decay rate of ||grad f||
+ * (FP64 full gradients at three checkpoints; a step whose gradient norm does
+ * not decrease at every checkpoint is rejected as unstable) and extrapolates
+ * to ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
+ * (f is lambda-strongly convex).  Smaller steps are probed while the
+ * estimate improves; a count whose probe alone would take longer than the
+ * best estimate so far ends the search.  The best pair is kept, the state is
+ * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair
+ * was stable. */
 int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);
 
 /* Derived numbers (instance 0, plus launch shape). */

@@ -26,6 +26,7 @@ constexpr int kMaxBlock = 512;
 constexpr double kAsyncStepFactor = 0.25;  // the update kernels are compiled for at most 512 threads per workgroup  // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
 
 struct Inst {
+    int fold = -1;            // held-out fold (-1: trains on every row)
     int64_t m = 0;
     int32_t* rows = nullptr;  // device, nullptr = identity
     double lambda = 0.0, gamma = 0.0, L = 0.0;
@@ -224,7 +225,7 @@ int relabel_columns(asaga_ctx* c) {
     if ((rc = dalloc(c, &c->rank, c->d))) return rc;
     if ((rc = dalloc(c, &c->colidx, c->nnz))) return rc;
     HIPCHK(c, launch_fill_i32(cnt, 0, c->d, c->st));
-    HIPCHK(c, launch_colcount(mat(c, false), nullptr, c->n, cnt, c->st));
+    HIPCHK(c, launch_colcount(mat(c, false), nullptr, c->n, cnt, false, c->st));
     std::vector<int32_t> h(c->d);
     HIPCHK(c, hipMemcpyAsync(h.data(), cnt, c->d * 4, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
@@ -240,32 +241,43 @@ int relabel_columns(asaga_ctx* c) {
 }
 
 // Column counts, D, Delta_r, L and gamma of one instance; zero its state.
-int setup_instance(asaga_ctx* c, Inst& I) {
+// An instance that trains on the same rows as an earlier one (same held-out
+// fold) shares that instance's counts, D and L.
+int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
     int rc;
-    if ((rc = dalloc(c, &I.cnt, c->d))) return rc;
-    if ((rc = dalloc(c, &I.D, c->d))) return rc;
     if ((rc = dalloc(c, &I.xa, 2 * c->d))) return rc;
     char* ap = nullptr;
     if ((rc = dalloc(c, &ap, I.m * (int64_t)(c->mixed ? 4 : 8)))) return rc;
     I.alpha = ap;
-
-    const MatArgs A = mat(c);
-    HIPCHK(c, launch_fill_i32(I.cnt, 0, c->d, c->st));
-    HIPCHK(c, launch_colcount(A, I.rows, I.m, I.cnt, c->st));
     int32_t stats[2] = {0, 0x7fffffff};
-    HIPCHK(c, hipMemcpyAsync(c->stats, stats, sizeof(stats), hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, launch_reweight(I.cnt, c->d, I.m, I.D, c->stats, c->st));
-    unsigned long long bits = 0;
-    HIPCHK(c, hipMemcpyAsync(c->maxbits, &bits, sizeof(bits), hipMemcpyHostToDevice, c->st));
-    HIPCHK(c, launch_rownorm_max(A, I.rows, I.m, c->maxbits, c->st));
-    HIPCHK(c, hipMemcpyAsync(stats, c->stats, sizeof(stats), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipMemcpyAsync(&bits, c->maxbits, sizeof(bits), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    double maxnorm;
-    std::memcpy(&maxnorm, &bits, 8);
-    I.delta_r = stats[0];
-    I.cnt_min = stats[1];
-    I.L = (c->loss == ASAGA_LOSS_LOGISTIC ? 0.25 : 1.0) * maxnorm + I.lambda;
+    if (same_rows) {
+        I.cnt = same_rows->cnt;
+        I.D = same_rows->D;
+        I.delta_r = same_rows->delta_r;
+        I.cnt_min = same_rows->cnt_min;
+        I.L = same_rows->L - same_rows->lambda + I.lambda;
+        stats[0] = (int32_t)I.delta_r;
+        stats[1] = I.cnt_min;
+    } else {
+        if ((rc = dalloc(c, &I.cnt, c->d))) return rc;
+        if ((rc = dalloc(c, &I.D, c->d))) return rc;
+        const MatArgs A = mat(c);
+        HIPCHK(c, launch_fill_i32(I.cnt, 0, c->d, c->st));
+        HIPCHK(c, launch_colcount(A, I.rows, I.m, I.cnt, true, c->st));
+        HIPCHK(c, hipMemcpyAsync(c->stats, stats, sizeof(stats), hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, launch_reweight(I.cnt, c->d, I.m, I.D, c->stats, c->st));
+        unsigned long long bits = 0;
+        HIPCHK(c, hipMemcpyAsync(c->maxbits, &bits, sizeof(bits), hipMemcpyHostToDevice, c->st));
+        HIPCHK(c, launch_rownorm_max(A, I.rows, I.m, c->maxbits, c->st));
+        HIPCHK(c, hipMemcpyAsync(stats, c->stats, sizeof(stats), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipMemcpyAsync(&bits, c->maxbits, sizeof(bits), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(c, hipStreamSynchronize(c->st));
+        double maxnorm;
+        std::memcpy(&maxnorm, &bits, 8);
+        I.delta_r = stats[0];
+        I.cnt_min = stats[1];
+        I.L = (c->loss == ASAGA_LOSS_LOGISTIC ? 0.25 : 1.0) * maxnorm + I.lambda;
+    }
     if (c->o.step > 0.0) {
         I.gamma = c->o.step;
     } else {
@@ -475,7 +487,14 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
             I.lambda = bt->inst_lambda[k];
             I.seed = o->seed + (uint64_t)k;
             const int f = bt->inst_fold[k];
-            if (f < 0) {
+            I.fold = f;
+            const Inst* same = nullptr;
+            for (const Inst& J : c->inst)
+                if (J.fold == f) same = &J;
+            if (same) {
+                I.m = same->m;
+                I.rows = same->rows;
+            } else if (f < 0) {
                 I.m = c->n;
             } else {
                 rows.clear();
@@ -498,8 +517,12 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
         }
         if ((rc = dalloc(c, &c->d_insts, (int64_t)c->inst.size()))) return bail(rc);
     }
-    for (auto& I : c->inst)
-        if ((rc = setup_instance(c, I))) return bail(rc);
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        const Inst* same = nullptr;
+        for (size_t q = 0; q < k && !same; ++q)
+            if (c->inst[q].fold == c->inst[k].fold) same = &c->inst[q];
+        if ((rc = setup_instance(c, c->inst[k], same))) return bail(rc);
+    }
     pick_shape(c);
     if ((rc = step([&]() -> int {
              HIPCHK(c, hipStreamSynchronize(c->st));
@@ -748,17 +771,16 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     if (cus <= 0) cus = 256;
     const int wpb = base.block / 64;
     auto round_waves = [&](int w) { return std::max(wpb, ((w + wpb - 1) / wpb) * wpb); };
+    // wavefront counts from the fastest epoch (most samples in flight) to the
+    // slowest; fewer samples in flight tolerate a larger step (Theorem 2)
     std::vector<UpdateShape> shapes;
-    for (int w : {cus * 4, cus * 8})
-        for (int h : {1024, 4096}) {
-            UpdateShape S = base;
-            S.waves = round_waves(w);
-            S.hot = (int)std::min<int64_t>(h, c->d);
-            S.tier = std::min(256, S.hot);
-            S.tier_every = 16;
-            shapes.push_back(S);
-        }
-    const double scales[] = {0.5, 0.25, 0.125, 0.0625};
+    for (int w = cus * 8; w >= std::max(wpb, cus / 8); w /= 2) {
+        UpdateShape S = base;
+        S.waves = round_waves(w);
+        if (!shapes.empty() && shapes.back().waves == S.waves) continue;
+        shapes.push_back(S);
+    }
+    const double scales[] = {1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625};
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -782,6 +804,13 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
             break;
         }
+        // every later shape is slower per epoch: none can beat the best once
+        // the probe alone takes longer than the best estimate
+        if ((double)probe_epochs * (double)ms * 1e-3 >= best.est_s) break;
+        // steps from the largest down, while the estimate improves: past the
+        // best stable step, smaller steps only converge more slowly
+        double shape_best = INFINITY;
+        int stable = 0;
         for (double sc : scales) {
             ++tried;
             I.gamma = serial_rule * sc;
@@ -798,7 +827,11 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             if (rc) break;
             int flag = 0;
             HIPCHK(c, hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
-            if (!ok || flag) continue;
+            if (!ok || flag) {
+                if (stable) break;
+                continue;
+            }
+            ++stable;
             // ||g|| decays like exp(-r t): r per epoch from the last two checkpoints
             const double r = 0.5 * std::log(g2[1] / g2[2]) / (double)(cps[2] - cps[1]);
             const double goal = 2.0 * I.lambda * target * f[2];
@@ -812,6 +845,8 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
                 best.gamma = I.gamma;
                 best.S = S;
             }
+            if (est_s >= shape_best) break;
+            shape_best = est_s;
         }
         if (rc) break;
     }

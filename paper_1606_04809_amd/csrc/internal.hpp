@@ -78,7 +78,10 @@ size_t update_lds_bytes(const UpdateShape& S);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, int64_t stride, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
-hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int32_t* cnt, hipStream_t st);
+// cnt_c += #{j < m : c in S_rows[j]}; hot_first: the most-used columns are the
+// lowest indices (after relabelling)
+hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int32_t* cnt, bool hot_first,
+                           hipStream_t st);
 // out[k] = rank[in[k]]
 hipError_t launch_relabel(const int32_t* in, int64_t nnz, const int32_t* rank, int32_t* out, hipStream_t st);
 // D_c = m / cnt_c (0 if cnt_c = 0); stats[0] = max cnt, stats[1] = min positive cnt

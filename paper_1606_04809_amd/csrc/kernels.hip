@@ -544,18 +544,56 @@ constexpr int kRowLanes = 16;
 
 __device__ __forceinline__ int64_t row_of(const int32_t* rows, int64_t j) { return rows ? (int64_t)rows[j] : j; }
 
-__global__ void k_colcount(MatArgs A, const int32_t* rows, int64_t m, int32_t* cnt) {
+// Column counts.  Columns in [c0, c0 + C) are counted in an LDS histogram
+// per workgroup (C <= kCountTile) and added to the global counts once per
+// workgroup, so the columns nearly every row touches do not serialise on
+// one address; with `rest` set, columns outside the tile are counted with
+// global atomics in the same pass.
+constexpr int kCountTile = 16384;
+
+__global__ void __launch_bounds__(1024) k_colcount(MatArgs A, const int32_t* rows, int64_t m, int32_t* cnt, int32_t c0,
+                                                   int32_t C, int rest) {
+    __shared__ int32_t h[kCountTile];
+    for (int q = threadIdx.x; q < C; q += blockDim.x) h[q] = 0;
+    __syncthreads();
     const int gl = threadIdx.x & (kRowLanes - 1);
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
     const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / kRowLanes;
     for (int64_t j = grp; j < m; j += ngrp) {
         const int64_t i = row_of(rows, j);
-        for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes) atomicAdd(cnt + A.colidx[k], 1);
+        for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes) {
+            const int32_t c = A.colidx[k];
+            const int32_t q = c - c0;
+            if (q >= 0 && q < C) atomicAdd(&h[q], 1);
+            else if (rest) atomicAdd(cnt + c, 1);
+        }
     }
+    __syncthreads();
+    for (int q = threadIdx.x; q < C; q += blockDim.x)
+        if (h[q]) atomicAdd(cnt + c0 + q, h[q]);
 }
 
-hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int32_t* cnt, hipStream_t st) {
-    k_colcount<<<grid_for(m * kRowLanes, 256), 256, 0, st>>>(A, rows, m, cnt);
+hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int32_t* cnt, bool hot_first,
+                           hipStream_t st) {
+    const int threads = 1024;
+    const int blocks = grid_for(m * kRowLanes, threads, 1024);
+    if (hot_first || A.d <= kCountTile) {
+        // one pass: [0, tile) in LDS, the rest by global atomics
+        const int32_t C = (int32_t)(A.d < kCountTile ? A.d : kCountTile);
+        k_colcount<<<blocks, threads, 0, st>>>(A, rows, m, cnt, 0, C, 1);
+        return hipGetLastError();
+    }
+    if (A.d <= 16 * (int64_t)kCountTile) {
+        // column order unknown (before relabelling): one LDS pass per tile
+        for (int64_t c0 = 0; c0 < A.d; c0 += kCountTile) {
+            const int32_t C = (int32_t)(A.d - c0 < kCountTile ? A.d - c0 : kCountTile);
+            k_colcount<<<blocks, threads, 0, st>>>(A, rows, m, cnt, (int32_t)c0, C, 0);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    k_colcount<<<blocks, threads, 0, st>>>(A, rows, m, cnt, 0, 0, 1);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 """Writes tests/golden/fstar.json: the optimum f* of each full-size workload,
 computed by the CPU oracle only (never by the HIP library).
 
-    python tests/golden/make_golden.py [config1 config2 config3 config4]
+    python tests/golden/make_golden.py [config1 config2 config3 config4 config5]
 
 * config1 (2,000 x 500 logistic): damped Newton on the dense objective;
   f* = oracle objective at the Newton point.
@@ -10,6 +10,10 @@ computed by the CPU oracle only (never by the HIP library).
 * config2, config4 (large logistic): the oracle's own serial Sparse SAGA run
   until the strong-convexity certificate ||grad f||^2/(2 lambda) <= 1e-12 f
   holds; f* lies in [f_lower, f_upper].
+
+* config5 (160 lambda x fold instances over the bfloat16 config-2 matrix):
+  the same certificate per instance, to 1e-11, one instance per worker
+  process.
 
 Each entry records the sha256 digest of the generated instance, so a test
 can check that it regenerated the same problem.
@@ -58,10 +62,52 @@ def entry_certificate(p, epochs_per_check=5):
             "converged": bool(r["converged"])}
 
 
+_BATCH = None
+
+
+def _batch_digest(B) -> str:
+    import hashlib
+    h = hashlib.sha256(B.problem.digest().encode())
+    for a in (B.row_fold, B.inst_fold, B.inst_lambda):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def _config5_instance(k):
+    t = time.time()
+    q = _BATCH.instance(k)
+    r = oracle.certified_fstar(q, tol=1e-11, check_every=5, max_epochs=600)
+    e = {"k": int(k), "fold": int(_BATCH.inst_fold[k]), "lambda": float(_BATCH.inst_lambda[k]), "m": int(q.n),
+         "f_star": r["f_lower"], "f_lower": r["f_lower"], "f_upper": r["f_upper"], "epochs": r["epochs"],
+         "converged": bool(r["converged"]), "seconds": round(time.time() - t, 1)}
+    print(f"  instance {k}: {e}", flush=True)
+    return e
+
+
+def entry_config5(workers):
+    import multiprocessing as mp
+    global _BATCH
+    _BATCH = datagen.config5()
+    order = sorted(range(_BATCH.n_inst), key=lambda k: _BATCH.inst_lambda[k])
+    with mp.get_context("fork").Pool(workers) as pool:
+        inst = sorted(pool.imap_unordered(_config5_instance, order), key=lambda e: e["k"])
+    return {"method": "oracle Sparse SAGA + strong-convexity certificate per instance", "instances": inst,
+            "converged": all(e["converged"] for e in inst), "digest": _batch_digest(_BATCH),
+            "n": _BATCH.problem.n, "d": _BATCH.problem.d, "nnz": _BATCH.problem.nnz, "n_inst": _BATCH.n_inst}
+
+
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
         t = time.time()
+        if name == "config5":
+            e = entry_config5(int(os.environ.get("GOLDEN_WORKERS", "8")))
+            e["seconds"] = round(time.time() - t, 1)
+            print(f"config5: converged {e['converged']} in {e['seconds']} s", flush=True)
+            data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+            data[name] = e
+            json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+            continue
         p = datagen.by_name(name)
         print(f"{name}: generated n={p.n} d={p.d} nnz={p.nnz} in {time.time() - t:.1f}s", flush=True)
         if name == "config1":
