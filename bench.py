@@ -67,6 +67,119 @@ def traffic_from_profile(per_launch_updates: int):
         return None
 
 
+def batched_leg(args, dev, stream):
+    """The lambda path x folds workload (160 instances over the bfloat16
+    config-2 matrix): all instances in one persistent kernel per epoch,
+    replayed from a captured hipGraph, mixed precision (FP32 x and alpha,
+    FP64 abar, bfloat16 values), autotuned wavefronts per instance and step;
+    each instance is switched off once it is within 1e-9 of its certified
+    optimum.  Then the same instances one by one with the plain FP64 async
+    kernel.  Times are kernel times between HIP events; the objective checks
+    between them are not counted."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    t = time.time()
+    B = datagen.config5()
+    p = B.problem
+    with open(os.path.join(ROOT, "tests", "golden", "fstar.json")) as fh:
+        gold = json.load(fh).get("config5")
+    if gold is None:
+        raise SystemExit("tests/golden/fstar.json has no config5 entry")
+    import hashlib
+    h = hashlib.sha256(p.digest().encode())
+    for a in (B.row_fold, B.inst_fold, B.inst_lambda):
+        h.update(np.ascontiguousarray(a).tobytes())
+    if gold["digest"] != h.hexdigest():
+        raise SystemExit("config5 batch differs from the one its optima were computed on")
+    fstar = np.array([e["f_lower"] for e in sorted(gold["instances"], key=lambda e: e["k"])])
+    ni = B.n_inst
+    log(f"generated config5: {ni} instances in {time.time() - t:.1f}s")
+
+    def to_dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    arrs = [to_dev(p.rowptr), to_dev(p.colidx), to_dev(p.val_bf16.view(np.int16)), to_dev(p.b)]
+    torch.cuda.synchronize()
+    g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
+                 precision=A.ASAGA_PREC_MIXED, stream=stream, batch=(B.row_fold, B.inst_fold, B.inst_lambda))
+    t = time.time()
+    rep = g.autotune(target=1e-9, probe_epochs=6)
+    tune = {"candidates": rep.candidates, "waves_per_instance": rep.waves, "hot_columns": rep.hot_columns,
+            "gamma_inst0": rep.gamma, "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs,
+            "tuning_wall_s": time.time() - t}
+    log(f"batched autotune: {tune}")
+    m = np.array([int(np.sum(B.row_fold != f)) for f in B.inst_fold])
+    active = np.ones(ni, dtype=np.uint8)
+    rel = np.full(ni, np.inf)
+    reached_at = np.zeros(ni)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kernel_s, epochs, updates, check = 0.0, 0, 0, 3
+    while active.any() and epochs < 600:
+        e0.record(stream)
+        g.epochs(check)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kernel_s += e0.elapsed_time(e1) / 1e3
+        updates += check * int(np.sum(m[active == 1]))
+        epochs += check
+        for k in np.nonzero(active)[0]:
+            rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
+            if rel[k] <= 1e-9:
+                active[k] = 0
+                reached_at[k] = epochs
+        g.set_active(active)
+    g.close()
+    del arrs
+    out = {"workload": "config5: 32 lambdas (1e-8..1e-2) x 5 uneven folds over the bfloat16 config-2 matrix, "
+                       "mixed precision (FP32 x/alpha, FP64 abar), one persistent kernel per epoch from a hipGraph",
+           "instances": ni, "reached": int(np.sum(rel <= 1e-9)), "epochs_max": epochs,
+           "epochs_median": float(np.median(reached_at[reached_at > 0])) if np.any(reached_at > 0) else None,
+           "seconds_to_1e-9_all": kernel_s, "updates": updates, "updates_per_s": updates / kernel_s,
+           "worst_rel_subopt": float(np.max(rel)), "autotune": tune}
+    log(f"batched: {out}")
+
+    # the same instances one by one: plain FP64 async kernel, library defaults
+    sel = np.unique(np.linspace(0, ni - 1, max(1, min(args.plain_instances, ni))).round().astype(int))
+    plain_s, plain_updates, plain_reached, plain_epochs = 0.0, 0, 0, []
+    for f in range(5):
+        ks = [k for k in sel if B.inst_fold[k] == f]
+        if not ks:
+            continue
+        sub = datagen.subproblem(p, B.rows(ks[0]))
+        arrs = [to_dev(a) for a in (sub.rowptr, sub.colidx, sub.val, sub.b)]
+        torch.cuda.synchronize()
+        for k in ks:
+            g = A.Solver(sub.n, sub.d, *arrs, float(B.inst_lambda[k]), loss=sub.loss, mode=A.ASAGA_MODE_ASYNC,
+                         stream=stream)
+            r, ep = np.inf, 0
+            while r > 1e-9 and ep < 600:
+                e0.record(stream)
+                g.epochs(1)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                plain_s += e0.elapsed_time(e1) / 1e3
+                plain_updates += sub.n
+                ep += 1
+                r = (g.objective() - fstar[k]) / fstar[k]
+            plain_reached += int(r <= 1e-9)
+            plain_epochs.append(ep)
+            g.close()
+        del arrs
+    scale = ni / len(sel)
+    out["plain_one_by_one"] = {
+        "instances_run": int(len(sel)), "reached": plain_reached, "seconds_to_1e-9": plain_s,
+        "seconds_to_1e-9_all_160_est": plain_s * scale, "updates_per_s": plain_updates / plain_s,
+        "epochs_median": float(np.median(plain_epochs)), "epochs_max": int(np.max(plain_epochs)),
+        "kernel": "plain FP64 async (k_update, library default shape and step), one instance at a time"}
+    out["batched_speedup_vs_plain"] = plain_s * scale / kernel_s
+    log(f"plain one by one: {out['plain_one_by_one']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +198,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape and step instead of asaga_autotune's choice")
+    ap.add_argument("--skip-batched", action="store_true", help="omit the batched lambda-path x folds leg")
+    ap.add_argument("--plain-instances", type=int, default=160,
+                    help="instances of the batch also solved one by one with the plain FP64 kernel (spread "
+                         "evenly over the 160)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -209,6 +326,9 @@ def main():
                "final_rel_subopt": rel}
         log(f"time to 1e-9: {tta}")
 
+    del dev_arrays
+    batched = None if args.skip_batched else batched_leg(args, dev, stream)
+
     # ---- CPU oracle on a bounded sample ------------------------------------------
     cpu = None
     if not args.skip_cpu:
@@ -248,6 +368,7 @@ def main():
                      "launch_ms": avg_launch_s * 1e3},
         "time_to_1e-9": tta,
         "autotune": tune,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

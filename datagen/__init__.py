@@ -254,7 +254,7 @@ def folds5(n: int, seed: int = 0) -> np.ndarray:
 def lambda_grid5(count: int = 32, lo_exp: float = -8.0, hi_exp: float = -2.0) -> np.ndarray:
     """Log-spaced regularisation path, 10^(lo + (hi-lo) k/(count-1))."""
     k = np.arange(count, dtype=np.float64)
-    return 10.0 ** (lo_exp + (hi_exp - lo_exp) * k / (count - 1))
+    return 10.0 ** (lo_exp + (hi_exp - lo_exp) * k / max(count - 1, 1))
 
 
 def subproblem(p: Problem, rows: np.ndarray, lam: float | None = None, name: str | None = None) -> Problem:

@@ -126,7 +126,9 @@ typedef struct asaga_opts {
     uint64_t seed;            /* sample-stream seed                                */
     int32_t mode;             /* ASAGA_MODE_*                                      */
     int32_t precision;        /* ASAGA_PREC_*                                      */
-    int32_t waves;            /* async: wavefronts in flight (0 = automatic)      */
+    int32_t waves;            /* async: wavefronts in flight, per instance in a
+                                 batch (0 = automatic: 8 per compute unit, or
+                                 64 per instance in a batch)                      */
     int32_t lanes_per_sample; /* async: 64, 32, 16 or 8 lanes per sample
                                  (0 = automatic from the mean row length)          */
     int32_t racy;             /* 1: plain read-modify-write instead of atomic adds
@@ -146,6 +148,10 @@ typedef struct asaga_opts {
                                  flushed every hot_tier_every rounds
                                  (0 = automatic, -1 = all hot columns every round) */
     int32_t hot_tier_every;   /* async: see hot_tier_columns (0 = automatic)      */
+    int32_t plain_launch;     /* batched: 1 launches each epoch's kernel directly;
+                                 0 (default) replays the epochs of one
+                                 asaga_epochs call as a captured hipGraph        */
+    int32_t reserved;         /* must be 0                                         */
     void* stream;             /* hipStream_t */
 } asaga_opts;
 
@@ -206,8 +212,21 @@ int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_o
                        const asaga_batch* batch);
 
 /* Apply n_epochs * n samples (n_k per instance in a batch), continuing the
- * sample stream.  Enqueued on the context's stream; returns without waiting. */
+ * sample stream.  Enqueued on the context's stream; returns without waiting
+ * for single-instance contexts.  A batched context runs one persistent
+ * kernel per epoch over every active instance; the n_epochs launches are
+ * captured once per distinct n_epochs (up to 64; larger counts run in pieces)
+ * into a hipGraph on a private stream and replayed on the context's stream
+ * (unless opts.plain_launch).  It waits for the previous call's work before
+ * rewriting the per-instance descriptors the kernels read. */
 int asaga_epochs(asaga_ctx* ctx, int64_t n_epochs);
+
+/* Batched contexts: switch instances on (1) or off (0) for later
+ * asaga_epochs calls (active is uint8_t[n_inst]).  An instance that is off
+ * keeps its state and sample counter unchanged; every instance starts on.
+ * The usual use: switch off each instance once its certificate or
+ * validation check has met the tolerance. */
+int asaga_set_active(asaga_ctx* ctx, const uint8_t* active);
 
 /* Apply `count` samples (single-instance contexts only). */
 int asaga_updates(asaga_ctx* ctx, int64_t count);
@@ -240,8 +259,9 @@ int asaga_set_state(asaga_ctx* ctx, int32_t inst, const double* x_host, const do
 int asaga_reanchor(asaga_ctx* ctx);
 
 /* Choose the number of wavefronts in flight and the step that reach
- * relative suboptimality `target` soonest on this problem (single-instance
- * async contexts; the other shape parameters stay as the context has them).
+ * relative suboptimality `target` soonest on this problem (async contexts;
+ * the other shape parameters stay as the context has them, except as said
+ * for batches below).
  * Fewer samples in flight tolerate a larger step (Theorem 2) but take longer
  * per epoch, so wavefront counts are tried from 8 per compute unit down to
  * 1/8 per compute unit, halving.  For each count it times one epoch, then,
@@ -254,7 +274,14 @@ int asaga_reanchor(asaga_ctx* ctx);
  * estimate improves; a count whose probe alone would take longer than the
  * best estimate so far ends the search.  The best pair is kept, the state is
  * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair
- * was stable. */
+ * was stable.
+ * Batched contexts: the candidates are wavefronts per instance (64 down to
+ * the workgroup's wave count, halving) times hot-set sizes (4096 and 1024
+ * columns), ordered by their measured time per epoch of the whole batch; a
+ * step is a common fraction of every instance's own rule; a pair is stable
+ * if every active instance's gradient norm decreases at every checkpoint,
+ * and its estimate is the slowest instance's epochs times the batch's time
+ * per epoch.  `waves` in the report is per instance. */
 int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);
 
 /* Derived numbers (instance 0, plus launch shape). */

@@ -71,7 +71,8 @@ class asaga_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("waves", ctypes.c_int32), ("lanes_per_sample", ctypes.c_int32),
                 ("racy", ctypes.c_int32), ("hot_columns", ctypes.c_int32), ("flush_every", ctypes.c_int32),
                 ("threads_per_block", ctypes.c_int32), ("hot_tier_columns", ctypes.c_int32),
-                ("hot_tier_every", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("hot_tier_every", ctypes.c_int32), ("plain_launch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class asaga_batch(ctypes.Structure):
@@ -102,6 +103,7 @@ _SIGS = {
     "asaga_init_batched": (ctypes.c_int, [ctypes.POINTER(_CTX), ctypes.POINTER(asaga_problem),
                                           ctypes.POINTER(asaga_opts), ctypes.POINTER(asaga_batch)]),
     "asaga_epochs": (ctypes.c_int, [_CTX, ctypes.c_int64]),
+    "asaga_set_active": (ctypes.c_int, [_CTX, _P]),
     "asaga_updates": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "asaga_objective": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
     "asaga_full_grad": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P]),
@@ -162,6 +164,11 @@ def asaga_init_batched(prob: asaga_problem, opts: asaga_opts, batch: asaga_batch
 
 def asaga_epochs(ctx, n_epochs: int):
     return _check(_lib.asaga_epochs(ctx, int(n_epochs)), ctx)
+
+
+def asaga_set_active(ctx, active):
+    a = np.ascontiguousarray(active, dtype=np.uint8)
+    return _check(_lib.asaga_set_active(ctx, a.ctypes.data), ctx)
 
 
 def asaga_updates(ctx, count: int):
@@ -266,7 +273,7 @@ class Solver:
     def __init__(self, n, d, rowptr, colidx, val, b, lam, loss=ASAGA_LOSS_LOGISTIC, val_dtype=None,
                  mode=ASAGA_MODE_SERIAL, precision=ASAGA_PREC_F64, step=0.0, seed=0, waves=0,
                  lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, threads_per_block=0,
-                 hot_tier_columns=0, hot_tier_every=0, stream=None, batch=None):
+                 hot_tier_columns=0, hot_tier_every=0, plain_launch=0, stream=None, batch=None):
         self.n, self.d = int(n), int(d)
         arrays = (rowptr, colidx, val, b)
         on_dev = [_is_torch_cuda(a) for a in arrays]
@@ -295,7 +302,7 @@ class Solver:
             stream = stream.cuda_stream
         self.opts = asaga_opts(float(step), int(seed), int(mode), int(precision), int(waves), int(lanes_per_sample),
                                int(racy), int(hot_columns), int(flush_every), int(threads_per_block),
-                               int(hot_tier_columns), int(hot_tier_every), stream)
+                               int(hot_tier_columns), int(hot_tier_every), int(plain_launch), 0, stream)
         if batch is None:
             self.ctx = asaga_init(self.prob, self.opts)
             self.n_inst = 1
@@ -315,6 +322,11 @@ class Solver:
 
     def updates(self, count: int):
         asaga_updates(self.ctx, count)
+
+    def set_active(self, active):
+        if len(active) != self.n_inst:
+            raise ValueError(f"expected {self.n_inst} flags")
+        asaga_set_active(self.ctx, active)
 
     def objective(self, inst: int = 0, x=None) -> float:
         return asaga_objective(self.ctx, inst, self.d, x)

@@ -21,15 +21,18 @@ namespace {
 thread_local std::string g_init_error = "no error";
 
 constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
-constexpr int kMaxHot = 4096;
-constexpr int kMaxBlock = 512;
-constexpr double kAsyncStepFactor = 0.25;  // the update kernels are compiled for at most 512 threads per workgroup  // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
+constexpr int kMaxHot = 4096;    // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
+constexpr int kMaxBlock = 512;   // the update kernels are compiled for at most 512 threads per workgroup
+constexpr double kAsyncStepFactor = 0.25;
+constexpr int64_t kMaxGraphEpochs = 64;  // epochs captured in one hipGraph
 
 struct Inst {
     int fold = -1;            // held-out fold (-1: trains on every row)
     int64_t m = 0;
     int32_t* rows = nullptr;  // device, nullptr = identity
     double lambda = 0.0, gamma = 0.0, L = 0.0;
+    double rule = 0.0;        // the serial step rule (or the caller's step)
+    bool active = true;       // batched: takes part in asaga_epochs
     int64_t delta_r = 0;
     int32_t cnt_min = 0;
     int32_t* cnt = nullptr;   // relabelled order
@@ -57,6 +60,14 @@ struct asaga_ctx {
     UpdateShape shape{};
     std::vector<Inst> inst;
     InstArgs* d_insts = nullptr;
+    // batched: captured epochs, keyed by the number of epochs per replay
+    hipStream_t cap = nullptr;
+    struct Captured {
+        int64_t epochs;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    std::vector<Captured> graphs;
     std::vector<void*> allocs;
     // scratch
     double* z = nullptr;      // [n]
@@ -173,6 +184,8 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
         return fail(nullptr, ASAGA_E_ARG, "hot_tier_every out of range");
     if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
         return fail(nullptr, ASAGA_E_ARG, "threads_per_block must be 0 or a multiple of 64 up to 512");
+    if (o->plain_launch != 0 && o->plain_launch != 1) return fail(nullptr, ASAGA_E_ARG, "plain_launch must be 0 or 1");
+    if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
     return ASAGA_OK;
 }
 
@@ -280,11 +293,13 @@ int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
     }
     if (c->o.step > 0.0) {
         I.gamma = c->o.step;
+        I.rule = c->o.step;
     } else {
         // gamma = min(1/(3L), 1/(lambda max_v D_v)); max_v D_v = m / min positive count
         const double dmax = stats[1] > 0 && stats[1] != 0x7fffffff ? (double)I.m / (double)stats[1] : 0.0;
         double g = 1.0 / (3.0 * I.L);
         if (I.lambda * dmax > 0.0 && 1.0 / (I.lambda * dmax) < g) g = 1.0 / (I.lambda * dmax);
+        I.rule = g;
         // Asynchronous updates read state that is older by the number of
         // samples in flight; the stable step shrinks with that delay
         // (Theorem 2).  A quarter of the serial rule is the default for the
@@ -324,7 +339,8 @@ void pick_shape(asaga_ctx* c) {
     if (waves == 0) {
         int cus = device_cu_count();
         if (cus <= 0) cus = 256;
-        waves = cus * 8;
+        // one instance: 8 wavefronts per compute unit; a batch: 64 per instance
+        waves = c->d_insts ? 64 : cus * 8;
     }
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
@@ -340,9 +356,20 @@ void pick_shape(asaga_ctx* c) {
     S.tier_every = c->o.hot_tier_every > 0 ? c->o.hot_tier_every : 16;
 }
 
+void drop_graphs(asaga_ctx* c) {
+    for (auto& g : c->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    c->graphs.clear();
+}
+
 int free_all(asaga_ctx* c) {
     if (!c) return ASAGA_OK;
     if (c->st) (void)hipStreamSynchronize(c->st);
+    drop_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    c->cap = nullptr;
     for (void* p : c->allocs) (void)hipFree(p);
     c->allocs.clear();
     return ASAGA_OK;
@@ -516,6 +543,11 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
             c->inst.push_back(I);
         }
         if ((rc = dalloc(c, &c->d_insts, (int64_t)c->inst.size()))) return bail(rc);
+        if ((rc = step([&]() -> int {
+                 HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+                 return ASAGA_OK;
+             })))
+            return bail(rc);
     }
     for (size_t k = 0; k < c->inst.size(); ++k) {
         const Inst* same = nullptr;
@@ -551,9 +583,76 @@ int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, XView* x) {
     return ASAGA_OK;
 }
 
+// The hipGraph that applies `epochs` epochs of every active instance: one
+// batched launch per epoch, epoch index e in 0..epochs-1 baked into each
+// node.  The descriptors it reads (d_insts) are rewritten before each replay.
+int epochs_graph(asaga_ctx* c, int64_t epochs, hipGraphExec_t* out) {
+    for (const auto& g : c->graphs)
+        if (g.epochs == epochs) {
+            *out = g.exec;
+            return ASAGA_OK;
+        }
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    hipError_t le = hipSuccess;
+    for (int64_t e = 0; e < epochs && le == hipSuccess; ++e)
+        le = launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), (uint64_t)e, c->shape, c->flag, c->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+    if (le != hipSuccess || ee != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return fail(c, ASAGA_E_HIP, std::string("capturing the epochs graph: ") +
+                                        hipGetErrorString(le != hipSuccess ? le : ee));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(c, ASAGA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    c->graphs.push_back({epochs, graph, exec});
+    *out = exec;
+    return ASAGA_OK;
+}
+
+// `epochs` epochs of every active instance of a batch
+int batched_piece(asaga_ctx* c, int64_t epochs) {
+    std::vector<InstArgs> h(c->inst.size());
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        const Inst& I = c->inst[k];
+        h[k] = inst_args(I, (uint64_t)I.t, I.active ? (uint64_t)I.m : 0);
+    }
+    // the previous call's launches read the descriptors: wait before overwriting them
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpyAsync(c->d_insts, h.data(), h.size() * sizeof(InstArgs), hipMemcpyHostToDevice, c->st));
+    if (c->o.plain_launch) {
+        for (int64_t e = 0; e < epochs; ++e)
+            HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), (uint64_t)e, c->shape, c->flag,
+                                             c->st));
+    } else {
+        hipGraphExec_t exec = nullptr;
+        int rc = epochs_graph(c, epochs, &exec);
+        if (rc) return rc;
+        HIPCHK(c, hipGraphLaunch(exec, c->st));
+    }
+    for (auto& I : c->inst)
+        if (I.active) I.t += epochs * I.m;
+    return ASAGA_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int asaga_set_active(asaga_ctx* c, const uint8_t* active) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!active) return fail(c, ASAGA_E_ARG, "NULL active mask");
+    if (!c->d_insts) return fail(c, ASAGA_E_STATE, "asaga_set_active needs a batched context");
+    for (size_t k = 0; k < c->inst.size(); ++k)
+        if (active[k] > 1) return fail(c, ASAGA_E_ARG, "active entries must be 0 or 1");
+    for (size_t k = 0; k < c->inst.size(); ++k) c->inst[k].active = active[k] != 0;
+    return ASAGA_OK;
+}
 
 int asaga_init(asaga_ctx** out, const asaga_problem* prob, const asaga_opts* opts) {
     return init_common(out, prob, opts, nullptr);
@@ -590,18 +689,12 @@ int asaga_epochs(asaga_ctx* c, int64_t n_epochs) {
         }
         return ASAGA_OK;
     }
-    std::vector<InstArgs> h(c->inst.size());
-    for (size_t k = 0; k < c->inst.size(); ++k) {
-        const Inst& I = c->inst[k];
-        h[k] = inst_args(I, (uint64_t)I.t, (uint64_t)I.m);
+    for (int64_t done = 0; done < n_epochs;) {
+        const int64_t e = std::min(n_epochs - done, kMaxGraphEpochs);
+        int rc = batched_piece(c, e);
+        if (rc) return rc;
+        done += e;
     }
-    // the previous call's launches read the descriptors: wait before overwriting them
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    HIPCHK(c, hipMemcpyAsync(c->d_insts, h.data(), h.size() * sizeof(InstArgs), hipMemcpyHostToDevice, c->st));
-    for (int64_t e = 0; e < n_epochs; ++e)
-        HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), (uint64_t)e, c->shape, c->flag, c->st));
-    for (auto& I : c->inst) I.t += n_epochs * I.m;
-    HIPCHK(c, hipStreamSynchronize(c->st));
     return ASAGA_OK;
 }
 
@@ -725,9 +818,9 @@ int asaga_reanchor(asaga_ctx* c) {
 
 namespace {
 
-// ||grad f(x)||^2 and f(x) at instance 0's current iterate (FP64)
-int grad_norm2(asaga_ctx* c, double* g2, double* f) {
-    const Inst& I = c->inst[0];
+// ||grad f(x)||^2 and f(x) at an instance's current iterate (FP64)
+int grad_norm2(asaga_ctx* c, int inst, double* g2, double* f) {
+    const Inst& I = c->inst[inst];
     const XView x = x_view(c, I);
     const MatArgs A = mat(c);
     HIPCHK(c, launch_rowdot(A, I.rows, I.m, x, c->z, c->st));
@@ -759,11 +852,144 @@ int reset_state(asaga_ctx* c) {
 
 }  // namespace
 
+namespace {
+
+// asaga_autotune for a batch: wavefronts per instance and hot-set size,
+// with a step that is a common fraction of every instance's own rule.
+int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune_report* rep) {
+    const UpdateShape base = c->shape;
+    const int wpb = base.block / 64;
+    const size_t ni = c->inst.size();
+    std::vector<UpdateShape> shapes;
+    for (int h : {4096, 1024}) {
+        const int hot = (int)std::min<int64_t>(h, c->d);
+        for (int w = 64; w >= wpb; w /= 2) {
+            UpdateShape S = base;
+            S.waves = std::max(wpb, (w / wpb) * wpb);
+            S.hot = hot;
+            S.tier = std::min(256, hot);
+            S.tier_every = 16;
+            bool dup = false;
+            for (const auto& T : shapes) dup = dup || (T.waves == S.waves && T.hot == S.hot);
+            if (!dup) shapes.push_back(S);
+        }
+    }
+    std::vector<double> saved_gamma(ni);
+    for (size_t k = 0; k < ni; ++k) saved_gamma[k] = c->inst[k].gamma;
+    auto restore = [&](const UpdateShape& S, double scale) {
+        c->shape = S;
+        drop_graphs(c);
+        for (size_t k = 0; k < ni; ++k) c->inst[k].gamma = scale > 0.0 ? c->inst[k].rule * scale : saved_gamma[k];
+        return reset_state(c);
+    };
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int rc = ASAGA_OK;
+    // time per epoch of the whole batch at each shape
+    std::vector<std::pair<float, size_t>> order;
+    for (size_t q = 0; q < shapes.size() && !rc; ++q) {
+        if ((rc = restore(shapes[q], 0.0))) break;
+        hipError_t he = hipEventRecord(e0, c->st);
+        if (he == hipSuccess && (rc = batched_piece(c, 1))) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, c->st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess) rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
+        order.push_back({ms, q});
+    }
+    std::sort(order.begin(), order.end());
+    const double scales[] = {1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125};
+    const int cps[3] = {probe_epochs / 3, 2 * probe_epochs / 3, probe_epochs};
+    struct Best {
+        double est_s = INFINITY, est_e = 0, ms = 0, scale = 0;
+        UpdateShape S{};
+    } best;
+    int tried = 0;
+    for (const auto& [ms, q] : order) {
+        if (rc) break;
+        if ((double)probe_epochs * (double)ms * 1e-3 >= best.est_s) break;
+        double shape_best = INFINITY;
+        int stable = 0;
+        for (double sc : scales) {
+            ++tried;
+            if ((rc = restore(shapes[q], sc))) break;
+            std::vector<double> g2(3 * ni, 0.0), f(3 * ni, 0.0);
+            int done = 0;
+            bool ok = true;
+            for (int k = 0; k < 3 && ok && !rc; ++k) {
+                if ((rc = asaga_epochs(c, cps[k] - done))) break;
+                done = cps[k];
+                for (size_t j = 0; j < ni && ok; ++j) {
+                    if (!c->inst[j].active) continue;
+                    double* gj = &g2[3 * j];
+                    if ((rc = grad_norm2(c, (int)j, &gj[k], &f[3 * j + k]))) break;
+                    ok = std::isfinite(gj[k]) && std::isfinite(f[3 * j + k]) && (k == 0 || gj[k] < gj[k - 1]);
+                }
+            }
+            if (rc) break;
+            int flag = 0;
+            HIPCHK(c, hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+            if (!ok || flag) {
+                if (stable) break;
+                continue;
+            }
+            ++stable;
+            // the slowest instance decides: epochs until its ||g||^2 <= 2 lambda target f
+            double est_e = (double)cps[2];
+            for (size_t j = 0; j < ni; ++j) {
+                if (!c->inst[j].active) continue;
+                const double* gj = &g2[3 * j];
+                const double r = 0.5 * std::log(gj[1] / gj[2]) / (double)(cps[2] - cps[1]);
+                const double goal = 2.0 * c->inst[j].lambda * target * f[3 * j + 2];
+                const double more = gj[2] > goal ? 0.5 * std::log(gj[2] / goal) / r : 0.0;
+                est_e = std::max(est_e, (double)cps[2] + more);
+            }
+            const double est_s = est_e * (double)ms * 1e-3;
+            if (est_s < best.est_s) {
+                best.est_s = est_s;
+                best.est_e = est_e;
+                best.ms = ms;
+                best.scale = sc;
+                best.S = shapes[q];
+            }
+            if (est_s >= shape_best) break;
+            shape_best = est_s;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) {
+        (void)restore(base, 0.0);
+        return rc;
+    }
+    if (!std::isfinite(best.est_s)) {
+        (void)restore(base, 0.0);
+        return fail(c, ASAGA_E_DIVERGED, "no probed launch shape and step reduced every instance's gradient norm steadily");
+    }
+    if ((rc = restore(best.S, best.scale))) return rc;
+    if (rep) {
+        rep->candidates = tried;
+        rep->waves = best.S.waves;
+        rep->hot_columns = best.S.hot;
+        rep->hot_tier_columns = best.S.tier;
+        rep->gamma = c->inst[0].gamma;
+        rep->ms_per_epoch = best.ms;
+        rep->est_epochs = best.est_e;
+        rep->est_seconds = best.est_s;
+    }
+    return ASAGA_OK;
+}
+
+}  // namespace
+
 int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune_report* rep) {
     if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
-    if (c->d_insts || c->shape.serial) return fail(c, ASAGA_E_STATE, "autotuning needs a single-instance async context");
+    if (c->shape.serial) return fail(c, ASAGA_E_STATE, "autotuning needs an async context");
     if (!(target > 0.0 && target < 1.0)) return fail(c, ASAGA_E_ARG, "target must be in (0, 1)");
     if (probe_epochs < 3 || probe_epochs > 1000) return fail(c, ASAGA_E_ARG, "probe_epochs must be in [3, 1000]");
+    if (c->d_insts) return autotune_batched(c, target, probe_epochs, rep);
     Inst& I = c->inst[0];
     const UpdateShape base = c->shape;
     const double serial_rule = c->o.step > 0.0 ? c->o.step : I.gamma / kAsyncStepFactor;
@@ -821,7 +1047,7 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             for (int k = 0; k < 3 && ok; ++k) {
                 if ((rc = asaga_updates(c, (int64_t)(cps[k] - done) * I.m))) break;
                 done = cps[k];
-                if ((rc = grad_norm2(c, &g2[k], &f[k]))) break;
+                if ((rc = grad_norm2(c, 0, &g2[k], &f[k]))) break;
                 ok = std::isfinite(g2[k]) && std::isfinite(f[k]) && (k == 0 || g2[k] < g2[k - 1]);
             }
             if (rc) break;

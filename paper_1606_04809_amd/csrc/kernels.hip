@@ -390,6 +390,7 @@ __global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArg
     const int inst = (int)(blockIdx.x / (unsigned)blocks_per_inst);
     if (inst >= n_inst) return;
     const InstArgs I = insts[inst];
+    if (I.count == 0) return;  // instance switched off: its state stays as it is
     const uint64_t groups = blockDim.x / G;
     const uint64_t slot = (blockIdx.x % (unsigned)blocks_per_inst) * groups + threadIdx.x / G;
     const uint64_t slots = (uint64_t)blocks_per_inst * groups;

@@ -62,7 +62,8 @@ def expect(code, **changes):
     kw = good()
     opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
                                                               "waves", "step", "loss", "hot_columns",
-                                                              "flush_every", "threads_per_block")}
+                                                              "flush_every", "threads_per_block",
+                                                              "plain_launch")}
     kw.update(changes)
     with pytest.raises(A.AsagaError) as ei:
         A.Solver(**kw, **opts)
@@ -103,6 +104,7 @@ def test_bad_arguments_are_rejected():
     expect(E, threads_per_block=100)
     expect(E, threads_per_block=2048)
     expect(E, threads_per_block=1024)
+    expect(E, plain_launch=2)
     expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
 
 
@@ -110,5 +112,7 @@ def test_null_context_calls_fail_cleanly():
     lib = ctypes.CDLL(A.LIB_PATH)
     lib.asaga_epochs.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     assert lib.asaga_epochs(None, 1) == A.ASAGA_E_ARG
+    lib.asaga_set_active.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.asaga_set_active(None, None) == A.ASAGA_E_ARG
     lib.asaga_free.argtypes = [ctypes.c_void_p]
     lib.asaga_free(None)

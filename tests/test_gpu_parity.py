@@ -258,6 +258,85 @@ def test_batched_instances_reach_their_own_optimum():
             assert rel_err(abar, oracle.SparseSaga(sub).memory_average(alpha)) < 1e-11
 
 
+def small_batch(n=12_000, d=3000, lams=(1e-4, 1e-3), folds=(0, 3)):
+    p = datagen.config2(n=n, d=d)
+    row_fold = datagen.folds5(p.n, seed=0)
+    inst_fold = np.array([f for f in folds for _ in lams], dtype=np.int32)
+    inst_lam = np.array([l for _ in folds for l in lams])
+    return p, row_fold, inst_fold, inst_lam
+
+
+def test_batched_graph_replays_match_plain_launches():
+    """One wavefront per instance makes each instance's run deterministic, so
+    the captured-graph replays must reproduce the directly launched epochs
+    bit for bit, across several replays with other work in between, and an
+    instance switched off must keep its state and counter."""
+    p, row_fold, inst_fold, inst_lam = small_batch(n=6000, d=1500)
+    m = [int(np.sum(row_fold != f)) for f in inst_fold]
+    kw = dict(mode=A.ASAGA_MODE_ASYNC, waves=1, threads_per_block=64, batch=(row_fold, inst_fold, inst_lam))
+    with A.from_problem(p, plain_launch=0, **kw) as gg, A.from_problem(p, plain_launch=1, **kw) as gp:
+        states = None
+        for r in range(5):
+            if r == 3:
+                mask = np.array([1, 0, 1, 1], dtype=np.uint8)
+                gg.set_active(mask)
+                gp.set_active(mask)
+            gg.epochs(2)
+            gp.epochs(2)
+            fg = [gg.objective(k) for k in range(4)]    # eager work between replays
+            fp = [gp.objective(k) for k in range(4)]
+            assert fg == fp, (r, fg, fp)
+            new = [gg.get_state(k, m=m[k]) for k in range(4)]
+            for k in range(4):
+                xg, ag, bg, tg = new[k]
+                xp, ap, bp, tp = gp.get_state(k, m=m[k])
+                assert tg == tp
+                assert np.array_equal(xg, xp) and np.array_equal(ag, ap) and np.array_equal(bg, bp), (r, k)
+                if r >= 3 and k == 1:
+                    xo, ao, bo, to = states[k]
+                    assert tg == to and np.array_equal(xg, xo) and np.array_equal(ag, ao)
+                else:
+                    assert tg == 2 * (r + 1) * m[k]
+            states = new
+        say(f"graph == plain over 5 calls; objectives {['%.6f' % f for f in fg]}")
+
+
+def test_batched_autotune_mixed_bf16_with_active_mask_reaches_1e9():
+    """The batched configuration of the lambda-path x folds workload, scaled
+    down: bfloat16 values, FP32 x and alpha with FP64 abar, autotuned
+    wavefronts per instance and step, instances switched off as they reach
+    1e-9 against their own oracle optimum (computed on the widened bfloat16
+    values, which are the instance)."""
+    B = datagen.config5(n=14_000, d=3000, n_lambda=1)
+    inst_fold = np.array([0, 3, 2, 1, 4], dtype=np.int32)
+    inst_lam = np.array([1e-5, 1e-4, 1e-3, 1e-2, 3e-5])
+    keep = inst_fold
+    q = B.problem
+    fstars = []
+    for f, lam in zip(inst_fold, inst_lam):
+        sub = datagen.subproblem(q, np.nonzero(B.row_fold != f)[0], lam=lam)
+        fstars.append(oracle.certified_fstar(sub, tol=1e-12, check_every=10)["f_lower"])
+    fstars = np.array(fstars)
+    with A.from_problem(q, bf16=True, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED,
+                        batch=(B.row_fold, inst_fold, inst_lam)) as g:
+        rep = g.autotune(target=1e-9, probe_epochs=6)
+        say(f"batched autotune: {rep.candidates} candidates, waves/inst {rep.waves} hot {rep.hot_columns} "
+            f"gamma[0] {rep.gamma:.4g} est {rep.est_epochs:.1f} epochs")
+        active = np.ones(len(keep), dtype=np.uint8)
+        rels = np.full(len(keep), np.inf)
+        for e in range(80):
+            g.epochs(5)
+            for k in np.nonzero(active)[0]:
+                rels[k] = (g.objective(int(k)) - fstars[k]) / fstars[k]
+            active[rels <= 1e-9] = 0
+            g.set_active(active)
+            if not active.any():
+                break
+        say(f"batched mixed: {5 * (e + 1)} epochs, rel {['%.1e' % r for r in rels]}")
+        assert np.all(rels <= 1e-9)
+        assert np.all(rels >= -1e-11)   # never below the certified optimum (beyond rounding)
+
+
 def test_mixed_precision_reaches_1e9():
     p = datagen.config2(n=20_000, d=5000)
     r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
