@@ -107,6 +107,7 @@ def batched_leg(args, dev, stream):
     g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
                  precision=A.ASAGA_PREC_MIXED, stream=stream, batch=(B.row_fold, B.inst_fold, B.inst_lambda))
     t = time.time()
+    log("batched autotune: probing wavefronts per instance, hot-set size and step")
     rep = g.autotune(target=1e-9, probe_epochs=6)
     tune = {"candidates": rep.candidates, "waves_per_instance": rep.waves, "hot_columns": rep.hot_columns,
             "gamma_inst0": rep.gamma, "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs,
@@ -132,6 +133,7 @@ def batched_leg(args, dev, stream):
                 active[k] = 0
                 reached_at[k] = epochs
         g.set_active(active)
+        log(f"batched: {epochs} epochs, {int(active.sum())} instances still active, kernel {kernel_s:.3f} s")
     g.close()
     del arrs
     out = {"workload": "config5: 32 lambdas (1e-8..1e-2) x 5 uneven folds over the bfloat16 config-2 matrix, "
@@ -167,6 +169,7 @@ def batched_leg(args, dev, stream):
                 r = (g.objective() - fstar[k]) / fstar[k]
             plain_reached += int(r <= 1e-9)
             plain_epochs.append(ep)
+            log(f"plain instance {k}: {ep} epochs, rel {r:.2e}, total kernel {plain_s:.3f} s")
             g.close()
         del arrs
     scale = ni / len(sel)

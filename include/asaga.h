@@ -126,9 +126,12 @@ typedef struct asaga_opts {
     uint64_t seed;            /* sample-stream seed                                */
     int32_t mode;             /* ASAGA_MODE_*                                      */
     int32_t precision;        /* ASAGA_PREC_*                                      */
-    int32_t waves;            /* async: wavefronts in flight, per instance in a
-                                 batch (0 = automatic: 8 per compute unit, or
-                                 64 per instance in a batch)                      */
+    int32_t waves;            /* async: wavefronts in flight (0 = automatic: 8
+                                 per compute unit, and at most n/64 samples in
+                                 flight).  Batches: wavefronts per
+                                 instance, fixed; 0 shares the device's
+                                 resident workgroups equally among the
+                                 instances still active (see asaga_epochs)       */
     int32_t lanes_per_sample; /* async: 64, 32, 16 or 8 lanes per sample
                                  (0 = automatic from the mean row length)          */
     int32_t racy;             /* 1: plain read-modify-write instead of atomic adds
@@ -137,7 +140,12 @@ typedef struct asaga_opts {
     int32_t hot_columns;      /* async: the H most-used columns whose writes each
                                  workgroup combines in LDS before adding them to
                                  the shared state (0 = automatic, -1 = none;
-                                 at most 4096)                                    */
+                                 at most 4096).  Automatic: 4096, less the
+                                 columns v with gamma lambda D_v W > 0.2 (W the
+                                 workgroups serving the instance): a hot
+                                 column's LDS view is refreshed only when the
+                                 workgroup next writes it, which delays its
+                                 regulariser step by about W of its updates   */
     int32_t flush_every;      /* async: samples each lane group applies between
                                  two flushes of those combined writes
                                  (0 = automatic)                                  */
@@ -147,7 +155,11 @@ typedef struct asaga_opts {
                                  round of flush_every samples; the others are
                                  flushed every hot_tier_every rounds
                                  (0 = automatic, -1 = all hot columns every round) */
-    int32_t hot_tier_every;   /* async: see hot_tier_columns (0 = automatic)      */
+    int32_t hot_tier_every;   /* async: see hot_tier_columns (0 = automatic: 16,
+                                 fewer when gamma * lambda * lane groups in
+                                 flight is large, since that tier's columns
+                                 are seen late by the other workgroups and
+                                 their regulariser step then lags)           */
     int32_t plain_launch;     /* batched: 1 launches each epoch's kernel directly;
                                  0 (default) replays the epochs of one
                                  asaga_epochs call as a captured hipGraph        */
@@ -213,12 +225,23 @@ int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_o
 
 /* Apply n_epochs * n samples (n_k per instance in a batch), continuing the
  * sample stream.  Enqueued on the context's stream; returns without waiting
- * for single-instance contexts.  A batched context runs one persistent
- * kernel per epoch over every active instance; the n_epochs launches are
- * captured once per distinct n_epochs (up to 64; larger counts run in pieces)
- * into a hipGraph on a private stream and replayed on the context's stream
- * (unless opts.plain_launch).  It waits for the previous call's work before
- * rewriting the per-instance descriptors the kernels read. */
+ * for single-instance contexts.
+ * A batched context runs one persistent kernel per epoch over every active
+ * instance.  With opts.waves = 0 the workgroups the device holds at once
+ * are shared equally among the active instances (each at least one, and at
+ * most n_k/64 samples in flight), so the instances still running take over
+ * the workgroups of those switched off;
+ * without opts.step, instance k then steps with
+ *     gamma_k = rule_k * min(cap, c / G_k),
+ * G_k the lane groups (samples in flight) serving it: the stable step
+ * shrinks with the delay (Theorem 2).  c and cap come from asaga_autotune;
+ * before it, c gives a single instance at 8 wavefronts per compute unit a
+ * quarter of its rule, and cap = 1.  The n_epochs launches are captured once
+ * per distinct n_epochs (up to 64; larger counts run in pieces) into a
+ * hipGraph on a private stream and replayed on the context's stream (unless
+ * opts.plain_launch).  It waits for the previous call's work before
+ * rewriting the per-instance descriptors and the workgroup map the kernels
+ * read. */
 int asaga_epochs(asaga_ctx* ctx, int64_t n_epochs);
 
 /* Batched contexts: switch instances on (1) or off (0) for later
@@ -258,30 +281,50 @@ int asaga_set_state(asaga_ctx* ctx, int32_t inst, const double* x_host, const do
  * leave in the running average (every instance). */
 int asaga_reanchor(asaga_ctx* ctx);
 
+/* Mixed-precision contexts: widen every instance's state to FP64 (x in
+ * place, alpha into a new FP64 array), recompute abar from alpha as
+ * asaga_reanchor does, and continue in FP64 from there: the final polish,
+ * since FP32 x cannot hold the optimum more closely than its own rounding
+ * (and FP32 atomic additions smaller than half an ulp are lost).  The
+ * context stays FP64 afterwards; no-op on FP64 contexts. */
+int asaga_widen(asaga_ctx* ctx);
+
 /* Choose the number of wavefronts in flight and the step that reach
  * relative suboptimality `target` soonest on this problem (async contexts;
  * the other shape parameters stay as the context has them, except as said
  * for batches below).
  * Fewer samples in flight tolerate a larger step (Theorem 2) but take longer
- * per epoch, so wavefront counts are tried from 8 per compute unit down to
- * 1/8 per compute unit, halving.  For each count it times one epoch, then,
- * for steps from the serial rule downwards by halves (to 1/64 of it), runs
+ * per epoch, so wavefront counts are tried from 8 per compute unit (at most
+ * n/64 samples in flight) down to 1/8 per compute unit, halving.  For each
+ * count it times one epoch, then, for steps from the serial rule downwards
+ * by halves (to 1/64 of it), runs
  * `probe_epochs` epochs from x = 0, measures the decay rate of ||grad f||
- * (FP64 full gradients at three checkpoints; a step whose gradient norm does
- * not decrease at every checkpoint is rejected as unstable) and extrapolates
+ * (FP64 full gradients at three checkpoints; a step whose squared gradient
+ * norm more than doubles between checkpoints, or does not decrease from the
+ * first to the last, is rejected as unstable) and extrapolates
  * to ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
  * (f is lambda-strongly convex).  Smaller steps are probed while the
  * estimate improves; a count whose probe alone would take longer than the
- * best estimate so far ends the search.  The best pair is kept, the state is
- * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair
- * was stable.
- * Batched contexts: the candidates are wavefronts per instance (64 down to
- * the workgroup's wave count, halving) times hot-set sizes (4096 and 1024
- * columns), ordered by their measured time per epoch of the whole batch; a
- * step is a common fraction of every instance's own rule; a pair is stable
- * if every active instance's gradient norm decreases at every checkpoint,
- * and its estimate is the slowest instance's epochs times the batch's time
- * per epoch.  `waves` in the report is per instance. */
+ * best estimate so far ends the search.  The best step of each of the three
+ * best counts then runs 3 * probe_epochs epochs, and the rate over its last
+ * third (closer to the asymptotic rate than the short probe's) decides; a
+ * run already certified at a checkpoint counts the epochs to the crossing,
+ * interpolated on log ||grad f||^2.  With FP32 x (ASAGA_PREC_MIXED) a
+ * gradient norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||)
+ * also counts as converged, so that stalling there is not taken for
+ * instability.  The best pair is kept, the state is reset to
+ * x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair was
+ * stable.
+ * Batched contexts (opts.step must be 0): the hot-set size (4096 or 1024
+ * columns) and the constant c of the step law of asaga_epochs are chosen
+ * on the active instance with the smallest lambda (the slowest, the last
+ * one running) alone on the device, by the same step ladder (with FP32 x,
+ * whose rounding floor is reached within a short probe, the largest stable
+ * step); then cap is
+ * the largest of 1, 1/2, 1/4, 1/8 with which no active instance is
+ * unstable in that sense with all of them running.
+ * `waves` in the report is per instance with all active instances
+ * running, `gamma` instance 0's step then. */
 int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);
 
 /* Derived numbers (instance 0, plus launch shape). */

@@ -111,6 +111,7 @@ _SIGS = {
     "asaga_get_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "asaga_set_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "asaga_reanchor": (ctypes.c_int, [_CTX]),
+    "asaga_widen": (ctypes.c_int, [_CTX]),
     "asaga_autotune": (ctypes.c_int, [_CTX, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(asaga_tune_report)]),
     "asaga_info_get": (ctypes.c_int, [_CTX, ctypes.POINTER(asaga_info)]),
     "asaga_sync": (ctypes.c_int, [_CTX]),
@@ -222,6 +223,10 @@ def asaga_set_state(ctx, inst: int, d: int, m: int, x=None, alpha=None, abar=Non
 
 def asaga_reanchor(ctx):
     return _check(_lib.asaga_reanchor(ctx), ctx)
+
+
+def asaga_widen(ctx):
+    return _check(_lib.asaga_widen(ctx), ctx)
 
 
 def asaga_autotune(ctx, target: float = 1e-9, probe_epochs: int = 9) -> asaga_tune_report:
@@ -345,6 +350,9 @@ class Solver:
 
     def reanchor(self):
         asaga_reanchor(self.ctx)
+
+    def widen(self):
+        asaga_widen(self.ctx)
 
     def autotune(self, target: float = 1e-9, probe_epochs: int = 9) -> asaga_tune_report:
         return asaga_autotune(self.ctx, target, probe_epochs)

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -36,6 +37,8 @@ struct Inst {
     int64_t delta_r = 0;
     int32_t cnt_min = 0;
     int32_t* cnt = nullptr;   // relabelled order
+    // host: running minimum of cnt over the relabelled order (non-increasing)
+    std::shared_ptr<std::vector<int32_t>> cnt_pmin;
     double* D = nullptr;      // relabelled order
     double* xa = nullptr;     // [2d] interleaved x / abar, relabelled order
     void* alpha = nullptr;    // [m]
@@ -60,10 +63,23 @@ struct asaga_ctx {
     UpdateShape shape{};
     std::vector<Inst> inst;
     InstArgs* d_insts = nullptr;
-    // batched: captured epochs, keyed by the number of epochs per replay
+    BlockMap* d_map = nullptr;   // batched: workgroup -> (instance, rank)
+    int64_t map_cap = 0;
+    // host copies of the last batched plan (kept until the next call, which
+    // first waits for the stream, so that the copies from them have ended)
+    std::vector<InstArgs> plan_h;
+    std::vector<BlockMap> plan_map;
+    // batched step law: gamma_k = rule_k * min(step_cap, step_groups / G_k),
+    // G_k the lane groups serving instance k (0: not calibrated, use the
+    // single-instance default at 8 wavefronts per compute unit)
+    double step_groups = 0.0, step_cap = 1.0;
+    // batched: captured epochs, keyed by epochs per replay, tier interval, grid
     hipStream_t cap = nullptr;
     struct Captured {
         int64_t epochs;
+        int tier_every, hot, tier;
+        int n_blocks;
+        const void* map;
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
@@ -215,6 +231,8 @@ InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
     a.seed = I.seed;
     a.t0 = t0;
     a.count = count;
+    a.blocks = 0;
+    a.reserved = 0;
     return a;
 }
 
@@ -265,6 +283,7 @@ int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
     int32_t stats[2] = {0, 0x7fffffff};
     if (same_rows) {
         I.cnt = same_rows->cnt;
+        I.cnt_pmin = same_rows->cnt_pmin;
         I.D = same_rows->D;
         I.delta_r = same_rows->delta_r;
         I.cnt_min = same_rows->cnt_min;
@@ -287,6 +306,10 @@ int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
         HIPCHK(c, hipStreamSynchronize(c->st));
         double maxnorm;
         std::memcpy(&maxnorm, &bits, 8);
+        auto pm = std::make_shared<std::vector<int32_t>>(c->d);
+        HIPCHK(c, hipMemcpy(pm->data(), I.cnt, c->d * 4, hipMemcpyDeviceToHost));
+        for (int64_t v = 1; v < c->d; ++v) (*pm)[v] = std::min((*pm)[v], (*pm)[v - 1]);
+        I.cnt_pmin = pm;
         I.delta_r = stats[0];
         I.cnt_min = stats[1];
         I.L = (c->loss == ASAGA_LOSS_LOGISTIC ? 0.25 : 1.0) * maxnorm + I.lambda;
@@ -308,6 +331,56 @@ int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
         I.gamma = g;
     }
     return zero_state(c, I);
+}
+
+// Automatic launch shapes keep the samples in flight for an instance at
+// most m/64 (at least one workgroup): the analysis of Section 3 assumes a
+// delay small against the number of samples, and well beyond that a short
+// probe can no longer tell a stable step from a slowly diverging one.
+int64_t max_groups_for(int64_t m) { return std::max<int64_t>(1, m / 64); }
+
+// A workgroup's LDS view of hot column v is refreshed when the workgroup
+// next writes v, so the column's regulariser step gamma lambda D_v x_v reads
+// a value about one of v's own updates old per workgroup serving the
+// instance (whatever v's count).  The hot set keeps only the leading columns
+// with gamma lambda D_v * workgroups <= 0.2 (D_v = m / cnt_v); the others
+// are read and written in global memory, where they are current.  (Measured
+// on the 560,000-row lambda-path instance at lambda = 4.8e-5 with 256
+// workgroups: 0.25 converges as fast as no hot set, 0.52 oscillates at
+// 1e-4.)  The caller's explicit hot_columns is kept as given.
+int stable_hot(const asaga_ctx* c, const Inst& I, int hot, double workgroups) {
+    if (c->o.hot_columns != 0 || hot <= 0 || !I.cnt_pmin) return hot;
+    const double gl = I.gamma * I.lambda * workgroups;
+    if (!(gl > 0.0)) return hot;
+    const double need = (double)I.m * gl / 0.2;  // cnt_v >= m gamma lambda W / 0.2
+    const auto& pm = *I.cnt_pmin;
+    // pm is non-increasing: count the leading columns with pm[v] >= need
+    int64_t lo = 0, hi = std::min<int64_t>(hot, (int64_t)pm.size());
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if ((double)pm[mid] >= need) lo = mid + 1;
+        else hi = mid;
+    }
+    return (int)lo;
+}
+
+// Rounds between flushes of the second hot tier.  A column of that tier is
+// seen by other workgroups up to tier_every * G samples late (G lane groups
+// in flight), and its regulariser step gamma lambda D_v x_v, applied on
+// 1/D_v of the samples, then lags by gamma lambda tier_every G in units of
+// its own decay: kept below 0.05 here, so that large-lambda instances
+// flush that tier more often (the caller's hot_tier_every, if set, wins).
+int tier_every_from(const asaga_ctx* c, double gamma_lambda_groups) {
+    if (c->o.hot_tier_every > 0) return c->o.hot_tier_every;
+    const double v = gamma_lambda_groups > 0.0 ? 0.05 / gamma_lambda_groups : 16.0;
+    return (int)std::max(1.0, std::min(16.0, std::floor(v)));
+}
+
+int tier_every_for(const asaga_ctx* c, const UpdateShape& S) {
+    double gl = 0.0;
+    for (const Inst& I : c->inst)
+        if (I.active) gl = std::max(gl, I.gamma * I.lambda);
+    return tier_every_from(c, gl * (double)S.waves * (64.0 / (double)S.lanes));
 }
 
 void pick_shape(asaga_ctx* c) {
@@ -339,8 +412,11 @@ void pick_shape(asaga_ctx* c) {
     if (waves == 0) {
         int cus = device_cu_count();
         if (cus <= 0) cus = 256;
-        // one instance: 8 wavefronts per compute unit; a batch: 64 per instance
-        waves = c->d_insts ? 64 : cus * 8;
+        // one instance: 8 wavefronts per compute unit, within the bound on
+        // samples in flight; a batch: planned per launch (64 per instance is
+        // only reported until then)
+        waves = c->d_insts ? 64
+                           : (int)std::min<int64_t>(cus * 8, std::max<int64_t>(1, max_groups_for(c->n) * lanes / 64));
     }
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
@@ -353,7 +429,7 @@ void pick_shape(asaga_ctx* c) {
     // the hot set every 16 rounds
     const int tier = c->o.hot_tier_columns == 0 ? 256 : c->o.hot_tier_columns < 0 ? S.hot : c->o.hot_tier_columns;
     S.tier = std::min(tier, S.hot);
-    S.tier_every = c->o.hot_tier_every > 0 ? c->o.hot_tier_every : 16;
+    S.tier_every = tier_every_for(c, S);
 }
 
 void drop_graphs(asaga_ctx* c) {
@@ -583,19 +659,96 @@ int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, XView* x) {
     return ASAGA_OK;
 }
 
-// The hipGraph that applies `epochs` epochs of every active instance: one
+// Work plan of one batched launch: which workgroups serve which instance,
+// each instance's step, and the tier interval.  With opts.waves set, every
+// instance keeps waves / (waves per workgroup) workgroups.  Otherwise the
+// grid is the device's resident capacity, shared equally among the active
+// instances (each at least one workgroup), so that instances that are
+// still running take over the workgroups of those switched off.  The step
+// of instance k without opts.step is rule_k * min(step_cap, step_groups /
+// G_k): samples in flight for an instance grow with its workgroups, and the
+// stable step shrinks in proportion (Theorem 2).
+int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
+    const size_t ni = c->inst.size();
+    UpdateShape S = c->shape;
+    const int wpb = S.block / 64;
+    std::vector<int> blocks(ni, 0);
+    std::vector<size_t> act;
+    for (size_t k = 0; k < ni; ++k)
+        if (c->inst[k].active) act.push_back(k);
+    int n_blocks = 0;
+    if (c->o.waves > 0) {
+        const int bpi = std::max(1, (S.waves + wpb - 1) / wpb);
+        n_blocks = (int)ni * bpi;
+        for (size_t k = 0; k < ni; ++k) blocks[k] = bpi;
+    } else if (!act.empty()) {
+        int res = batched_resident_blocks(S, c->val_dtype);
+        if (res <= 0) res = std::max(1, device_cu_count());
+        const int share = std::max<int>(res, (int)act.size());
+        const int q = share / (int)act.size(), r = share % (int)act.size();
+        const int64_t gpb = S.block / S.lanes;  // lane groups per workgroup
+        for (size_t a = 0; a < act.size(); ++a) {
+            const int64_t cap = std::max<int64_t>(1, max_groups_for(c->inst[act[a]].m) / gpb);
+            blocks[act[a]] = (int)std::min<int64_t>(cap, q + ((int)a < r ? 1 : 0));
+            n_blocks += blocks[act[a]];
+        }
+    }
+    std::vector<BlockMap>& map = c->plan_map;
+    map.assign(n_blocks, BlockMap{-1, 0});
+    if (c->o.waves > 0) {
+        for (int b = 0; b < n_blocks; ++b) map[b] = BlockMap{b / blocks[0], b % blocks[0]};
+    } else {
+        int b = 0;
+        for (size_t k : act)
+            for (int r = 0; r < blocks[k]; ++r) map[b++] = BlockMap{(int32_t)k, r};
+    }
+    double sg = c->step_groups;
+    if (sg <= 0.0) {
+        int cus = device_cu_count();
+        if (cus <= 0) cus = 256;
+        sg = kAsyncStepFactor * (double)cus * 8.0 * (64.0 / (double)S.lanes);
+    }
+    double glg = 0.0;
+    std::vector<InstArgs>& h = c->plan_h;
+    h.resize(ni);
+    for (size_t k = 0; k < ni; ++k) {
+        Inst& I = c->inst[k];
+        const double groups = (double)blocks[k] * (double)S.block / (double)S.lanes;
+        if (c->o.step <= 0.0 && blocks[k] > 0) I.gamma = I.rule * std::min(c->step_cap, sg / groups);
+        h[k] = inst_args(I, (uint64_t)I.t, I.active ? (uint64_t)I.m : 0);
+        h[k].blocks = blocks[k];
+        if (I.active) glg = std::max(glg, I.gamma * I.lambda * groups);
+    }
+    S.tier_every = tier_every_from(c, glg);
+    for (size_t k : act) S.hot = stable_hot(c, c->inst[k], S.hot, (double)blocks[k]);
+    S.tier = std::min(S.tier, S.hot);
+    *Sout = S;
+    if ((int64_t)n_blocks > c->map_cap) {
+        drop_graphs(c);
+        BlockMap* m = nullptr;
+        int rc = dalloc(c, &m, (int64_t)n_blocks);
+        if (rc) return rc;
+        c->d_map = m;
+        c->map_cap = n_blocks;
+    }
+    return ASAGA_OK;
+}
+
+// The hipGraph that applies `epochs` epochs of the planned launch: one
 // batched launch per epoch, epoch index e in 0..epochs-1 baked into each
-// node.  The descriptors it reads (d_insts) are rewritten before each replay.
-int epochs_graph(asaga_ctx* c, int64_t epochs, hipGraphExec_t* out) {
+// node.  The descriptors and block map it reads are rewritten before each
+// replay.
+int epochs_graph(asaga_ctx* c, int64_t epochs, const UpdateShape& S, int n_blocks, hipGraphExec_t* out) {
     for (const auto& g : c->graphs)
-        if (g.epochs == epochs) {
+        if (g.epochs == epochs && g.tier_every == S.tier_every && g.hot == S.hot && g.tier == S.tier &&
+            g.n_blocks == n_blocks && g.map == c->d_map) {
             *out = g.exec;
             return ASAGA_OK;
         }
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
     hipError_t le = hipSuccess;
     for (int64_t e = 0; e < epochs && le == hipSuccess; ++e)
-        le = launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), (uint64_t)e, c->shape, c->flag, c->cap);
+        le = launch_updates_batched(mat(c), c->d_insts, c->d_map, n_blocks, (uint64_t)e, S, c->flag, c->cap);
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -610,29 +763,30 @@ int epochs_graph(asaga_ctx* c, int64_t epochs, hipGraphExec_t* out) {
         (void)hipGraphDestroy(graph);
         return fail(c, ASAGA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     }
-    c->graphs.push_back({epochs, graph, exec});
+    c->graphs.push_back({epochs, S.tier_every, S.hot, S.tier, n_blocks, c->d_map, graph, exec});
     *out = exec;
     return ASAGA_OK;
 }
 
 // `epochs` epochs of every active instance of a batch
 int batched_piece(asaga_ctx* c, int64_t epochs) {
-    std::vector<InstArgs> h(c->inst.size());
-    for (size_t k = 0; k < c->inst.size(); ++k) {
-        const Inst& I = c->inst[k];
-        h[k] = inst_args(I, (uint64_t)I.t, I.active ? (uint64_t)I.m : 0);
-    }
     // the previous call's launches read the descriptors: wait before overwriting them
     HIPCHK(c, hipStreamSynchronize(c->st));
-    HIPCHK(c, hipMemcpyAsync(c->d_insts, h.data(), h.size() * sizeof(InstArgs), hipMemcpyHostToDevice, c->st));
+    UpdateShape S;
+    int rc = plan_batched(c, &S);
+    if (rc) return rc;
+    const int n_blocks = (int)c->plan_map.size();
+    if (n_blocks == 0) return ASAGA_OK;
+    HIPCHK(c, hipMemcpyAsync(c->d_insts, c->plan_h.data(), c->plan_h.size() * sizeof(InstArgs),
+                             hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->d_map, c->plan_map.data(), c->plan_map.size() * sizeof(BlockMap),
+                             hipMemcpyHostToDevice, c->st));
     if (c->o.plain_launch) {
         for (int64_t e = 0; e < epochs; ++e)
-            HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, (int)c->inst.size(), (uint64_t)e, c->shape, c->flag,
-                                             c->st));
+            HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, c->d_map, n_blocks, (uint64_t)e, S, c->flag, c->st));
     } else {
         hipGraphExec_t exec = nullptr;
-        int rc = epochs_graph(c, epochs, &exec);
-        if (rc) return rc;
+        if ((rc = epochs_graph(c, epochs, S, n_blocks, &exec))) return rc;
         HIPCHK(c, hipGraphLaunch(exec, c->st));
     }
     for (auto& I : c->inst)
@@ -668,11 +822,17 @@ int asaga_updates(asaga_ctx* c, int64_t count) {
     if (count < 0) return fail(c, ASAGA_E_ARG, "negative update count");
     if (c->d_insts) return fail(c, ASAGA_E_STATE, "asaga_updates needs a single-instance context");
     Inst& I = c->inst[0];
+    UpdateShape S = c->shape;
+    if (!S.serial) {
+        S.hot = stable_hot(c, I, S.hot, (double)((S.waves * 64 + S.block - 1) / S.block));
+        S.tier = std::min(S.tier, S.hot);
+        S.tier_every = tier_every_for(c, S);
+    }
     // serial launches are cut into pieces of at most 2^18 updates
-    const int64_t piece = c->shape.serial ? ((int64_t)1 << 18) : count;
+    const int64_t piece = S.serial ? ((int64_t)1 << 18) : count;
     for (int64_t done = 0; done < count;) {
         const int64_t k = count - done < piece ? count - done : piece;
-        HIPCHK(c, launch_updates(mat(c), inst_args(I, (uint64_t)I.t, (uint64_t)k), c->shape, c->flag, c->st));
+        HIPCHK(c, launch_updates(mat(c), inst_args(I, (uint64_t)I.t, (uint64_t)k), S, c->flag, c->st));
         I.t += k;
         done += k;
     }
@@ -816,10 +976,35 @@ int asaga_reanchor(asaga_ctx* c) {
     return ASAGA_OK;
 }
 
+int asaga_widen(asaga_ctx* c) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!c->mixed) return ASAGA_OK;
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::vector<void*> wide(c->inst.size());
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        double* a = nullptr;
+        int rc = dalloc(c, &a, c->inst[k].m);
+        if (rc) return rc;
+        wide[k] = a;
+    }
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        Inst& I = c->inst[k];
+        HIPCHK(c, launch_widen_x_slots(I.xa, c->d, c->st));
+        HIPCHK(c, launch_widen_f32(static_cast<const float*>(I.alpha), I.m, static_cast<double*>(wide[k]), c->st));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (size_t k = 0; k < c->inst.size(); ++k) c->inst[k].alpha = wide[k];
+    c->mixed = false;
+    c->shape.mixed = false;
+    drop_graphs(c);
+    // abar from the memory it averages, in FP64
+    return asaga_reanchor(c);
+}
+
 namespace {
 
 // ||grad f(x)||^2 and f(x) at an instance's current iterate (FP64)
-int grad_norm2(asaga_ctx* c, int inst, double* g2, double* f) {
+int grad_norm2(asaga_ctx* c, int inst, double* g2, double* f, double* x2 = nullptr) {
     const Inst& I = c->inst[inst];
     const XView x = x_view(c, I);
     const MatArgs A = mat(c);
@@ -837,7 +1022,34 @@ int grad_norm2(asaga_ctx* c, int inst, double* g2, double* f) {
     HIPCHK(c, hipStreamSynchronize(c->st));
     *f = s[0] / (double)I.m + 0.5 * I.lambda * s[1];
     *g2 = s[2];
+    if (x2) *x2 = s[1];
     return ASAGA_OK;
+}
+
+// A probe's run is unstable if ||grad f||^2 more than doubles between two
+// checkpoints or shows no net decrease from the first to the last; single
+// steps without decrease are noise of the asynchronous updates.
+bool probe_unstable(const double* g2, int k) {
+    if (k == 0) return false;
+    return g2[k] > 2.0 * g2[k - 1] || (k == 2 && !(g2[2] < g2[0]));
+}
+
+// decay rate per epoch of ||grad f|| over the last two checkpoints, else
+// over the whole probe (0 if there was none)
+double probe_rate(const double* g2, const int* cps) {
+    double r = 0.5 * std::log(g2[1] / g2[2]) / (double)(cps[2] - cps[1]);
+    if (!(r > 0.0)) r = 0.5 * std::log(g2[0] / g2[2]) / (double)(cps[2] - cps[0]);
+    return r > 0.0 ? r : 0.0;
+}
+
+// ||grad f||^2 an autotuning probe accepts as converged: the strong-convexity
+// certificate of relative suboptimality `target`, or, with FP32 x, the floor
+// its rounding leaves (a gradient error of about 8 * 2^-24 * L * ||x||).
+double probe_goal(const asaga_ctx* c, const Inst& I, double target, double f, double x2) {
+    const double cert = 2.0 * I.lambda * target * f;
+    if (!c->mixed) return cert;
+    const double e = 8.0 * 0x1p-24 * I.L;
+    return std::max(cert, e * e * x2);
 }
 
 int reset_state(asaga_ctx* c) {
@@ -854,126 +1066,180 @@ int reset_state(asaga_ctx* c) {
 
 namespace {
 
-// asaga_autotune for a batch: wavefronts per instance and hot-set size,
-// with a step that is a common fraction of every instance's own rule.
+// asaga_autotune for a batch: the hot-set size and the step law.  The law
+// gamma_k = rule_k * min(step_cap, step_groups / G_k) is calibrated where it
+// matters most, on the instance with the smallest lambda (the slowest, the
+// last one running) given the whole device, as a single-instance step
+// ladder; then step_cap is checked with every instance running.
 int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune_report* rep) {
-    const UpdateShape base = c->shape;
-    const int wpb = base.block / 64;
+    if (c->o.step > 0.0) return fail(c, ASAGA_E_STATE, "batched autotuning chooses the steps: opts.step must be 0");
     const size_t ni = c->inst.size();
-    std::vector<UpdateShape> shapes;
-    for (int h : {4096, 1024}) {
-        const int hot = (int)std::min<int64_t>(h, c->d);
-        for (int w = 64; w >= wpb; w /= 2) {
-            UpdateShape S = base;
-            S.waves = std::max(wpb, (w / wpb) * wpb);
-            S.hot = hot;
-            S.tier = std::min(256, hot);
-            S.tier_every = 16;
-            bool dup = false;
-            for (const auto& T : shapes) dup = dup || (T.waves == S.waves && T.hot == S.hot);
-            if (!dup) shapes.push_back(S);
-        }
+    std::vector<bool> was_active(ni);
+    size_t cal = ni;
+    for (size_t k = 0; k < ni; ++k) {
+        was_active[k] = c->inst[k].active;
+        if (was_active[k] && (cal == ni || c->inst[k].lambda < c->inst[cal].lambda)) cal = k;
     }
-    std::vector<double> saved_gamma(ni);
-    for (size_t k = 0; k < ni; ++k) saved_gamma[k] = c->inst[k].gamma;
-    auto restore = [&](const UpdateShape& S, double scale) {
-        c->shape = S;
+    if (cal == ni) return fail(c, ASAGA_E_STATE, "no active instance to tune on");
+    const UpdateShape base = c->shape;
+    const double base_groups = c->step_groups, base_cap = c->step_cap;
+    auto set_active = [&](bool solo) {
+        for (size_t k = 0; k < ni; ++k) c->inst[k].active = solo ? k == cal : (bool)was_active[k];
+    };
+    auto restore = [&]() {
+        c->shape = base;
+        c->step_groups = base_groups;
+        c->step_cap = base_cap;
+        set_active(false);
         drop_graphs(c);
-        for (size_t k = 0; k < ni; ++k) c->inst[k].gamma = scale > 0.0 ? c->inst[k].rule * scale : saved_gamma[k];
-        return reset_state(c);
+        (void)reset_state(c);
     };
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    int rc = ASAGA_OK;
-    // time per epoch of the whole batch at each shape
-    std::vector<std::pair<float, size_t>> order;
-    for (size_t q = 0; q < shapes.size() && !rc; ++q) {
-        if ((rc = restore(shapes[q], 0.0))) break;
+    int rc = ASAGA_OK, tried = 0;
+    const int cps[3] = {probe_epochs / 3, 2 * probe_epochs / 3, probe_epochs};
+    // Run from zero with checkpoints cps; false if some active instance's
+    // ||grad f|| did not decrease at every checkpoint before it was already
+    // certified; *est_e: epochs until the slowest one reaches
+    // ||g||^2 <= 2 lambda target f at its last measured rate.
+    auto probe = [&](double* est_e) -> bool {
+        if ((rc = reset_state(c))) return false;
+        std::vector<double> g2(3 * ni, 0.0), f(3 * ni, 0.0), goal(ni, 0.0);
+        std::vector<int> reached(ni, -1);
+        int done = 0;
+        for (int k = 0; k < 3; ++k) {
+            if ((rc = asaga_epochs(c, cps[k] - done))) return false;
+            done = cps[k];
+            for (size_t j = 0; j < ni; ++j) {
+                if (!c->inst[j].active || reached[j] >= 0) continue;
+                double* gj = &g2[3 * j];
+                double x2 = 0.0;
+                if ((rc = grad_norm2(c, (int)j, &gj[k], &f[3 * j + k], &x2))) return false;
+                if (!(std::isfinite(gj[k]) && std::isfinite(f[3 * j + k]))) return false;
+                goal[j] = probe_goal(c, c->inst[j], target, f[3 * j + k], x2);
+                if (gj[k] <= goal[j]) reached[j] = k;
+                else if (probe_unstable(gj, k)) return false;
+            }
+        }
+        int flag = 0;
+        const hipError_t he = hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost);
+        if (he != hipSuccess) {
+            rc = fail(c, ASAGA_E_HIP, std::string("autotune flag: ") + hipGetErrorString(he));
+            return false;
+        }
+        if (flag) return false;
+        double e = (double)cps[2];
+        for (size_t j = 0; j < ni; ++j) {
+            if (!c->inst[j].active || reached[j] >= 0) continue;
+            const double* gj = &g2[3 * j];
+            const double r = probe_rate(gj, cps);
+            if (r == 0.0) return false;
+            e = std::max(e, (double)cps[2] + (gj[2] > goal[j] ? 0.5 * std::log(gj[2] / goal[j]) / r : 0.0));
+        }
+        *est_e = e;
+        return true;
+    };
+    struct Best {
+        double est_s = INFINITY, est_e = 0, ms = 0, groups = 0;
+        UpdateShape S{};
+    } best;
+    // 1. the calibration instance alone on the device, per hot-set size
+    set_active(true);
+    std::vector<int> hots;
+    for (int h : {4096, 1024}) {
+        const int hot = (int)std::min<int64_t>(h, c->d);
+        if (std::find(hots.begin(), hots.end(), hot) == hots.end()) hots.push_back(hot);
+    }
+    const double scales[] = {1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625};
+    for (int hot : hots) {
+        UpdateShape S = base;
+        S.hot = hot;
+        S.tier = std::min(256, hot);
+        c->shape = S;
+        drop_graphs(c);
+        int res = batched_resident_blocks(S, c->val_dtype);
+        if (res <= 0) res = std::max(1, device_cu_count());
+        const int64_t gpb = S.block / S.lanes;
+        const int64_t cal_blocks = std::min<int64_t>(res, std::max<int64_t>(1, max_groups_for(c->inst[cal].m) / gpb));
+        const double groups = (double)(cal_blocks * gpb);
+        if ((rc = reset_state(c))) break;
         hipError_t he = hipEventRecord(e0, c->st);
         if (he == hipSuccess && (rc = batched_piece(c, 1))) break;
         if (he == hipSuccess) he = hipEventRecord(e1, c->st);
         if (he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0.0f;
         if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
-        order.push_back({ms, q});
-    }
-    std::sort(order.begin(), order.end());
-    const double scales[] = {1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125};
-    const int cps[3] = {probe_epochs / 3, 2 * probe_epochs / 3, probe_epochs};
-    struct Best {
-        double est_s = INFINITY, est_e = 0, ms = 0, scale = 0;
-        UpdateShape S{};
-    } best;
-    int tried = 0;
-    for (const auto& [ms, q] : order) {
-        if (rc) break;
-        if ((double)probe_epochs * (double)ms * 1e-3 >= best.est_s) break;
+        if (he != hipSuccess) {
+            rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
         double shape_best = INFINITY;
-        int stable = 0;
+        bool stable = false;
         for (double sc : scales) {
             ++tried;
-            if ((rc = restore(shapes[q], sc))) break;
-            std::vector<double> g2(3 * ni, 0.0), f(3 * ni, 0.0);
-            int done = 0;
-            bool ok = true;
-            for (int k = 0; k < 3 && ok && !rc; ++k) {
-                if ((rc = asaga_epochs(c, cps[k] - done))) break;
-                done = cps[k];
-                for (size_t j = 0; j < ni && ok; ++j) {
-                    if (!c->inst[j].active) continue;
-                    double* gj = &g2[3 * j];
-                    if ((rc = grad_norm2(c, (int)j, &gj[k], &f[3 * j + k]))) break;
-                    ok = std::isfinite(gj[k]) && std::isfinite(f[3 * j + k]) && (k == 0 || gj[k] < gj[k - 1]);
-                }
-            }
+            c->step_groups = sc * groups;
+            c->step_cap = 1.0;
+            double est_e = 0.0;
+            const bool ok = probe(&est_e);
             if (rc) break;
-            int flag = 0;
-            HIPCHK(c, hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
-            if (!ok || flag) {
+            if (!ok) {
                 if (stable) break;
                 continue;
             }
-            ++stable;
-            // the slowest instance decides: epochs until its ||g||^2 <= 2 lambda target f
-            double est_e = (double)cps[2];
-            for (size_t j = 0; j < ni; ++j) {
-                if (!c->inst[j].active) continue;
-                const double* gj = &g2[3 * j];
-                const double r = 0.5 * std::log(gj[1] / gj[2]) / (double)(cps[2] - cps[1]);
-                const double goal = 2.0 * c->inst[j].lambda * target * f[3 * j + 2];
-                const double more = gj[2] > goal ? 0.5 * std::log(gj[2] / goal) / r : 0.0;
-                est_e = std::max(est_e, (double)cps[2] + more);
-            }
+            stable = true;
             const double est_s = est_e * (double)ms * 1e-3;
-            if (est_s < best.est_s) {
-                best.est_s = est_s;
-                best.est_e = est_e;
-                best.ms = ms;
-                best.scale = sc;
-                best.S = shapes[q];
-            }
-            if (est_s >= shape_best) break;
+            if (est_s < best.est_s) best = Best{est_s, est_e, (double)ms, sc * groups, S};
+            // FP32 x reaches its rounding floor within a short probe whatever
+            // the step, so the rates cannot rank the steps: the largest stable
+            // one is kept (in the step-limited regime it converges fastest)
+            if (c->mixed || est_s >= shape_best) break;
             shape_best = est_s;
+        }
+        if (rc) break;
+    }
+    // 2. every instance running: the largest stable cap
+    double cap = 0.0;
+    if (!rc && std::isfinite(best.est_s)) {
+        set_active(false);
+        c->shape = best.S;
+        c->step_groups = best.groups;
+        drop_graphs(c);
+        for (double cp : {1.0, 0.5, 0.25, 0.125}) {
+            ++tried;
+            c->step_cap = cp;
+            double est_e = 0.0;
+            const bool ok = probe(&est_e);
+            if (rc) break;
+            if (ok) {
+                cap = cp;
+                break;
+            }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) {
-        (void)restore(base, 0.0);
+        restore();
         return rc;
     }
-    if (!std::isfinite(best.est_s)) {
-        (void)restore(base, 0.0);
-        return fail(c, ASAGA_E_DIVERGED, "no probed launch shape and step reduced every instance's gradient norm steadily");
+    if (!std::isfinite(best.est_s) || cap == 0.0) {
+        restore();
+        return fail(c, ASAGA_E_DIVERGED, "no probed hot-set size and step law reduced every gradient norm steadily");
     }
-    if ((rc = restore(best.S, best.scale))) return rc;
+    c->step_cap = cap;
+    set_active(false);
+    drop_graphs(c);
+    if ((rc = reset_state(c))) return rc;
+    UpdateShape S;
+    if ((rc = plan_batched(c, &S))) return rc;  // sets every instance's step for the full batch
     if (rep) {
+        int n_act = 0, res = batched_resident_blocks(S, c->val_dtype);
+        for (size_t k = 0; k < ni; ++k) n_act += c->inst[k].active ? 1 : 0;
         rep->candidates = tried;
-        rep->waves = best.S.waves;
-        rep->hot_columns = best.S.hot;
-        rep->hot_tier_columns = best.S.tier;
+        rep->waves = std::max(1, res / std::max(1, n_act)) * (S.block / 64);
+        rep->hot_columns = S.hot;
+        rep->hot_tier_columns = S.tier;
         rep->gamma = c->inst[0].gamma;
         rep->ms_per_epoch = best.ms;
         rep->est_epochs = best.est_e;
@@ -1000,7 +1266,8 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     // wavefront counts from the fastest epoch (most samples in flight) to the
     // slowest; fewer samples in flight tolerate a larger step (Theorem 2)
     std::vector<UpdateShape> shapes;
-    for (int w = cus * 8; w >= std::max(wpb, cus / 8); w /= 2) {
+    const int wmax = (int)std::min<int64_t>(cus * 8, std::max<int64_t>(1, max_groups_for(I.m) * base.lanes / 64));
+    for (int w = wmax; w >= std::max(wpb, std::min(wmax, cus / 8)); w /= 2) {
         UpdateShape S = base;
         S.waves = round_waves(w);
         if (!shapes.empty() && shapes.back().waves == S.waves) continue;
@@ -1010,11 +1277,51 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    struct Best {
+    struct Cand {
         double est_s = INFINITY, est_e = 0, ms = 0, gamma = 0;
         UpdateShape S{};
     } best;
+    std::vector<Cand> stable_cands;
     int tried = 0, rc = ASAGA_OK;
+    // Run from x = 0 at step I.gamma with checkpoints cps[0..2]: false if
+    // ||grad f|| did not decrease at every checkpoint; else the estimated
+    // epochs to ||g||^2 <= 2 lambda target f, with ||g|| taken to decay like
+    // exp(-r t) at the rate r of the last two checkpoints.
+    auto probe = [&](const int* cps, double* est_e) -> bool {
+        if ((rc = reset_state(c))) return false;
+        double g2[3], f[3], x2 = 0.0;
+        int done = 0;
+        for (int k = 0; k < 3; ++k) {
+            if ((rc = asaga_updates(c, (int64_t)(cps[k] - done) * I.m))) return false;
+            done = cps[k];
+            if ((rc = grad_norm2(c, 0, &g2[k], &f[k], &x2))) return false;
+            if (!(std::isfinite(g2[k]) && std::isfinite(f[k]))) return false;
+            // already certified: later checkpoints would only see the noise
+            // floor; the crossing is interpolated on log ||g||^2
+            const double goal_k = probe_goal(c, I, target, f[k], x2);
+            if (g2[k] <= goal_k) {
+                *est_e = (double)cps[k];
+                if (k > 0 && g2[k - 1] > goal_k && g2[k] > 0.0)
+                    *est_e = (double)cps[k - 1] +
+                             (double)(cps[k] - cps[k - 1]) * std::log(g2[k - 1] / goal_k) / std::log(g2[k - 1] / g2[k]);
+                return true;
+            }
+            if (probe_unstable(g2, k)) return false;
+        }
+        int flag = 0;
+        const hipError_t he = hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost);
+        if (he != hipSuccess) {
+            rc = fail(c, ASAGA_E_HIP, std::string("autotune flag: ") + hipGetErrorString(he));
+            return false;
+        }
+        if (flag) return false;
+        const double r = probe_rate(g2, cps);
+        if (r == 0.0) return false;
+        const double goal = probe_goal(c, I, target, f[2], x2);
+        const double more = g2[2] > goal ? 0.5 * std::log(g2[2] / goal) / r : 0.0;
+        *est_e = (double)cps[2] + more;
+        return true;
+    };
     const int cps[3] = {probe_epochs / 3, 2 * probe_epochs / 3, probe_epochs};
     for (const UpdateShape& S : shapes) {
         c->shape = S;
@@ -1040,41 +1347,50 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         for (double sc : scales) {
             ++tried;
             I.gamma = serial_rule * sc;
-            if ((rc = reset_state(c))) break;
-            double g2[3], f[3];
-            int done = 0;
-            bool ok = true;
-            for (int k = 0; k < 3 && ok; ++k) {
-                if ((rc = asaga_updates(c, (int64_t)(cps[k] - done) * I.m))) break;
-                done = cps[k];
-                if ((rc = grad_norm2(c, 0, &g2[k], &f[k]))) break;
-                ok = std::isfinite(g2[k]) && std::isfinite(f[k]) && (k == 0 || g2[k] < g2[k - 1]);
-            }
+            double est_e = 0.0;
+            const bool ok = probe(cps, &est_e);
             if (rc) break;
-            int flag = 0;
-            HIPCHK(c, hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
-            if (!ok || flag) {
+            if (!ok) {
                 if (stable) break;
                 continue;
             }
             ++stable;
-            // ||g|| decays like exp(-r t): r per epoch from the last two checkpoints
-            const double r = 0.5 * std::log(g2[1] / g2[2]) / (double)(cps[2] - cps[1]);
-            const double goal = 2.0 * I.lambda * target * f[2];
-            const double more = g2[2] > goal ? 0.5 * std::log(g2[2] / goal) / r : 0.0;
-            const double est_e = (double)cps[2] + more;
             const double est_s = est_e * (double)ms * 1e-3;
-            if (est_s < best.est_s) {
-                best.est_s = est_s;
-                best.est_e = est_e;
-                best.ms = ms;
-                best.gamma = I.gamma;
-                best.S = S;
-            }
+            stable_cands.push_back({est_s, est_e, (double)ms, I.gamma, S});
+            if (est_s < best.est_s) best = stable_cands.back();
             if (est_s >= shape_best) break;
             shape_best = est_s;
         }
         if (rc) break;
+    }
+    // The short probes see mostly the fast early decrease; the three best
+    // candidates run three times longer, and the rate over their last third
+    // decides.
+    if (!rc && stable_cands.size() > 1) {
+        std::sort(stable_cands.begin(), stable_cands.end(),
+                  [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });
+        // the best step of each wavefront count, then the three best counts
+        std::vector<Cand> fin;
+        for (const Cand& k : stable_cands) {
+            bool seen = false;
+            for (const Cand& q : fin) seen = seen || q.S.waves == k.S.waves;
+            if (!seen) fin.push_back(k);
+        }
+        fin.resize(std::min<size_t>(3, fin.size()));
+        stable_cands = fin;
+        const int cps3[3] = {probe_epochs, 2 * probe_epochs, 3 * probe_epochs};
+        best = Cand{};
+        for (const Cand& k : stable_cands) {
+            ++tried;
+            c->shape = k.S;
+            I.gamma = k.gamma;
+            double est_e = 0.0;
+            const bool ok = probe(cps3, &est_e);
+            if (rc) break;
+            if (!ok) continue;
+            const double est_s = est_e * k.ms * 1e-3;
+            if (est_s < best.est_s) best = Cand{est_s, est_e, k.ms, k.gamma, k.S};
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1117,13 +1433,18 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->gamma = I.gamma;
     out->lambda = I.lambda;
     out->waves = c->shape.waves;
+    if (c->d_insts && c->o.waves == 0) {
+        int n_act = 0, res = batched_resident_blocks(c->shape, c->val_dtype);
+        for (const Inst& J : c->inst) n_act += J.active ? 1 : 0;
+        out->waves = std::max(1, res / std::max(1, n_act)) * (c->shape.block / 64);
+    }
     out->lanes_per_sample = c->shape.lanes;
     out->n_inst = (int32_t)c->inst.size();
     out->hot_columns = c->shape.hot;
     out->flush_every = c->shape.flush;
     out->threads_per_block = c->shape.block;
     out->hot_tier_columns = c->shape.tier;
-    out->hot_tier_every = c->shape.tier_every;
+    out->hot_tier_every = c->shape.serial ? c->shape.tier_every : tier_every_for(c, c->shape);
     out->reserved = 0;
     return ASAGA_OK;
 }

@@ -27,7 +27,16 @@ struct InstArgs {
     double inv_m;
     uint64_t seed;
     uint64_t t0;          // sample counter of the first update of this launch
-    uint64_t count;       // updates this launch applies to the instance
+    uint64_t count;       // updates this launch applies to the instance (0: skip it)
+    int32_t blocks;       // batched: workgroups serving the instance
+    int32_t reserved;
+};
+
+// Batched launches: workgroup b serves instance inst, as its rank-th
+// workgroup (inst < 0: idle).
+struct BlockMap {
+    int32_t inst;
+    int32_t rank;
 };
 
 struct MatArgs {
@@ -68,10 +77,13 @@ struct XView {
 };
 
 hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag, hipStream_t st);
-// Instance k applies samples t0_k + epoch*count_k .. t0_k + (epoch+1)*count_k - 1;
-// S.waves is the number of wavefronts per instance.
-hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, int n_inst, uint64_t epoch,
-                                  const UpdateShape& S, int* flag, hipStream_t st);
+// One persistent grid of n_blocks workgroups over all instances, workgroup b
+// serving instance dev_map[b].inst; instance k applies samples
+// t0_k + epoch*count_k .. t0_k + (epoch+1)*count_k - 1.
+hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, const BlockMap* dev_map,
+                                  int n_blocks, uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st);
+// workgroups of the batched update kernel that fit on the device at once
+int batched_resident_blocks(const UpdateShape& S, int32_t val_dtype);
 size_t update_lds_bytes(const UpdateShape& S);
 
 // initialisation
@@ -117,6 +129,8 @@ hipError_t launch_gather_view(XView x, const int32_t* rank, int64_t d, double* o
 hipError_t launch_scatter_slots(const double* in, const int32_t* rank, int64_t d, void* slot, int64_t stride, bool f32,
                                 hipStream_t st);
 hipError_t launch_widen_f32(const float* in, int64_t count, double* out, hipStream_t st);
+// the FP32 x of the mixed-precision layout (low half of xa[2c]) widened in place to FP64
+hipError_t launch_widen_x_slots(double* xa, int64_t d, hipStream_t st);
 hipError_t launch_narrow_f64(const double* in, int64_t count, float* out, hipStream_t st);
 
 hipError_t launch_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, int64_t* out, hipStream_t st);

@@ -382,18 +382,18 @@ __global__ void __launch_bounds__(512) k_update(MatArgs A, InstArgs I, HotArgs H
     run_slots<G, kPasses, SERIAL, RACY, MIXED, VT>(A, I, I.t0, slot, slots, H, flag);
 }
 
-// Many instances in one persistent grid: blocks_per_inst consecutive
-// workgroups serve one instance.
+// Many instances in one persistent grid: the block map says which instance
+// each workgroup serves and as which of that instance's workgroups.
 template <int G, bool MIXED, typename VT>
-__global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArgs* insts, int n_inst,
-                                                        int blocks_per_inst, uint64_t epoch, HotArgs H, int* flag) {
-    const int inst = (int)(blockIdx.x / (unsigned)blocks_per_inst);
-    if (inst >= n_inst) return;
-    const InstArgs I = insts[inst];
-    if (I.count == 0) return;  // instance switched off: its state stays as it is
+__global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArgs* insts, const BlockMap* map,
+                                                        uint64_t epoch, HotArgs H, int* flag) {
+    const BlockMap bm = map[blockIdx.x];
+    if (bm.inst < 0) return;
+    const InstArgs I = insts[bm.inst];
+    if (I.count == 0 || bm.rank >= I.blocks) return;  // instance switched off: its state stays as it is
     const uint64_t groups = blockDim.x / G;
-    const uint64_t slot = (blockIdx.x % (unsigned)blocks_per_inst) * groups + threadIdx.x / G;
-    const uint64_t slots = (uint64_t)blocks_per_inst * groups;
+    const uint64_t slot = (uint64_t)bm.rank * groups + threadIdx.x / G;
+    const uint64_t slots = (uint64_t)I.blocks * groups;
     run_slots<G, kPasses, false, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, H, flag);
 }
 
@@ -464,47 +464,76 @@ hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape
 }
 
 template <int G, bool MIXED, typename VT>
-static hipError_t launch_batched_g(const MatArgs& A, const InstArgs* insts, int n_inst, uint64_t epoch,
-                                   const UpdateShape& S, int* flag, hipStream_t st) {
-    const int threads = S.block;
-    const int bpi = (S.waves * 64 + threads - 1) / threads;
-    const int blocks = bpi * n_inst;
+static hipError_t launch_batched_g(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
+                                   uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
     const size_t lds = update_lds_bytes(S);
     if (lds > 65536) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_batched<G, MIXED, VT>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_update_batched<G, MIXED, VT><<<blocks, threads, lds, st>>>(A, insts, n_inst, bpi, epoch, hot_args(S), flag);
+    k_update_batched<G, MIXED, VT><<<n_blocks, S.block, lds, st>>>(A, insts, map, epoch, hot_args(S), flag);
     return hipGetLastError();
 }
 
+template <int G, bool MIXED, typename VT>
+static int resident_g(const UpdateShape& S) {
+    const size_t lds = update_lds_bytes(S);
+    const void* fn = reinterpret_cast<const void*>(&k_update_batched<G, MIXED, VT>);
+    if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, S.block, lds) != hipSuccess) return 0;
+    return per_cu * device_cu_count();
+}
+
 template <bool MIXED, typename VT>
-static hipError_t launch_batched_t(const MatArgs& A, const InstArgs* insts, int n_inst, uint64_t epoch,
-                                   const UpdateShape& S, int* flag, hipStream_t st) {
+static hipError_t launch_batched_t(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
+                                   uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
     switch (S.lanes) {
-        case 64: return launch_batched_g<64, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
-        case 32: return launch_batched_g<32, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
-        case 16: return launch_batched_g<16, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
-        case 8: return launch_batched_g<8, MIXED, VT>(A, insts, n_inst, epoch, S, flag, st);
+        case 64: return launch_batched_g<64, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 32: return launch_batched_g<32, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 16: return launch_batched_g<16, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 8: return launch_batched_g<8, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, int n_inst, uint64_t epoch,
-                                  const UpdateShape& S, int* flag, hipStream_t st) {
+template <bool MIXED, typename VT>
+static int resident_t(const UpdateShape& S) {
+    switch (S.lanes) {
+        case 64: return resident_g<64, MIXED, VT>(S);
+        case 32: return resident_g<32, MIXED, VT>(S);
+        case 16: return resident_g<16, MIXED, VT>(S);
+        case 8: return resident_g<8, MIXED, VT>(S);
+        default: return 0;
+    }
+}
+
+hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, const BlockMap* dev_map,
+                                  int n_blocks, uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
+    if (n_blocks <= 0) return hipSuccess;
     switch (A.val_dtype) {
         case ASAGA_VAL_F64:
-            return S.mixed ? launch_batched_t<true, double>(A, dev_insts, n_inst, epoch, S, flag, st)
-                           : launch_batched_t<false, double>(A, dev_insts, n_inst, epoch, S, flag, st);
+            return S.mixed ? launch_batched_t<true, double>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st)
+                           : launch_batched_t<false, double>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
         case ASAGA_VAL_F32:
-            return S.mixed ? launch_batched_t<true, float>(A, dev_insts, n_inst, epoch, S, flag, st)
-                           : launch_batched_t<false, float>(A, dev_insts, n_inst, epoch, S, flag, st);
+            return S.mixed ? launch_batched_t<true, float>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st)
+                           : launch_batched_t<false, float>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
         case ASAGA_VAL_BF16:
-            return S.mixed ? launch_batched_t<true, uint16_t>(A, dev_insts, n_inst, epoch, S, flag, st)
-                           : launch_batched_t<false, uint16_t>(A, dev_insts, n_inst, epoch, S, flag, st);
+            return S.mixed ? launch_batched_t<true, uint16_t>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st)
+                           : launch_batched_t<false, uint16_t>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
     }
     return hipErrorInvalidValue;
+}
+
+int batched_resident_blocks(const UpdateShape& S, int32_t val_dtype) {
+    switch (val_dtype) {
+        case ASAGA_VAL_F64: return S.mixed ? resident_t<true, double>(S) : resident_t<false, double>(S);
+        case ASAGA_VAL_F32: return S.mixed ? resident_t<true, float>(S) : resident_t<false, float>(S);
+        case ASAGA_VAL_BF16: return S.mixed ? resident_t<true, uint16_t>(S) : resident_t<false, uint16_t>(S);
+    }
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -769,8 +798,20 @@ hipError_t launch_alpha_coef(const void* alpha, bool f32, int64_t m, double scal
     return hipGetLastError();
 }
 
+// out[c * stride] += sum_j coef_j a_rows[j],c.  The most-used columns
+// [0, hot) (the lowest labels after relabelling) are summed per workgroup in
+// LDS and added to global memory once per workgroup; the others take one
+// global atomic per entry.  Without this, every row's atomic on the handful
+// of columns nearly all rows touch serialises on a few cache lines.
+constexpr int kScatterHot = 4096;
+constexpr int kScatterBlocks = 1024;
+
 template <typename VT>
-__global__ void k_scatter(MatArgs A, const int32_t* rows, int64_t m, const double* coef, double* out, int64_t stride) {
+__global__ void __launch_bounds__(256) k_scatter(MatArgs A, const int32_t* rows, int64_t m, const double* coef,
+                                                 double* out, int64_t stride, int hot) {
+    __shared__ double acc[kScatterHot];
+    for (int q = threadIdx.x; q < hot; q += blockDim.x) acc[q] = 0.0;
+    __syncthreads();
     const VT* val = static_cast<const VT*>(A.val);
     const int gl = threadIdx.x & (kRowLanes - 1);
     const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes;
@@ -778,19 +819,31 @@ __global__ void k_scatter(MatArgs A, const int32_t* rows, int64_t m, const doubl
     for (int64_t j = grp; j < m; j += ngrp) {
         const int64_t i = row_of(rows, j);
         const double cj = coef[j];
-        for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes)
-            __hip_atomic_fetch_add(out + (int64_t)A.colidx[k] * stride, cj * widen(val[k]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        for (int64_t k = A.rowptr[i] + gl; k < A.rowptr[i + 1]; k += kRowLanes) {
+            const int32_t c = A.colidx[k];
+            const double w = cj * widen(val[k]);
+            if (c < hot)
+                atomicAdd(&acc[c], w);
+            else
+                __hip_atomic_fetch_add(out + (int64_t)c * stride, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < hot; q += blockDim.x) {
+        const double w = acc[q];
+        if (w != 0.0) __hip_atomic_fetch_add(out + (int64_t)q * stride, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 hipError_t launch_scatter(const MatArgs& A, const int32_t* rows, int64_t m, const double* coef, double* out,
                           int64_t stride, hipStream_t st) {
-    const int blocks = grid_for(m * kRowLanes, 256);
+    if (m <= 0) return hipSuccess;
+    const int blocks = grid_for(m * kRowLanes, 256, kScatterBlocks);
+    const int hot = (int)(A.d < kScatterHot ? A.d : kScatterHot);
     switch (A.val_dtype) {
-        case ASAGA_VAL_F64: k_scatter<double><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride); break;
-        case ASAGA_VAL_F32: k_scatter<float><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride); break;
-        case ASAGA_VAL_BF16: k_scatter<uint16_t><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride); break;
+        case ASAGA_VAL_F64: k_scatter<double><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride, hot); break;
+        case ASAGA_VAL_F32: k_scatter<float><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride, hot); break;
+        case ASAGA_VAL_BF16: k_scatter<uint16_t><<<blocks, 256, 0, st>>>(A, rows, m, coef, out, stride, hot); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -888,6 +941,20 @@ __global__ void k_widen(const float* in, int64_t count, double* out) {
 __global__ void k_narrow(const double* in, int64_t count, float* out) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
         out[k] = (float)in[k];
+}
+
+// x_c stored as FP32 in the low half of slot xa[2c] -> FP64 in the whole slot
+__global__ void k_widen_x_slots(double* xa, int64_t d) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < d; c += (int64_t)gridDim.x * blockDim.x) {
+        const float v = reinterpret_cast<const float*>(xa + 2 * c)[0];
+        xa[2 * c] = (double)v;
+    }
+}
+
+hipError_t launch_widen_x_slots(double* xa, int64_t d, hipStream_t st) {
+    if (d <= 0) return hipSuccess;
+    k_widen_x_slots<<<grid_for(d, 256), 256, 0, st>>>(xa, d);
+    return hipGetLastError();
 }
 
 hipError_t launch_widen_f32(const float* in, int64_t count, double* out, hipStream_t st) {
