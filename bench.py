@@ -9,11 +9,14 @@ scalar gradient, scatter of x and abar, memory update).
 
 Prints one JSON line: updates/s, algorithmic HBM GB/s against the 8 TB/s
 roofline (per-launch time measured with HIP events on the library's
-stream), the time to 1e-9 relative suboptimality from a cold start, and the
-CPU oracle timed on a bounded sample on this host.
+stream), the time to 1e-9 relative suboptimality from a cold start, the
+batched leg (160 lambda x fold instances over the same matrix in bfloat16,
+mixed precision, to 1e-9 each, against the same instances solved one by
+one with the plain FP64 kernel), and the CPU oracle timed on a bounded
+sample on this host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-tta]
-                    [--copy-calibration]
+                    [--skip-batched] [--plain-instances N] [--copy-calibration]
 
 --copy-calibration adds a plain 1 GiB device-to-device copy (known bytes
 read and written) so that a profiler's per-dispatch byte counters can be
@@ -192,7 +195,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle leg")
     ap.add_argument("--skip-tta", action="store_true", help="omit the time-to-accuracy leg")
-    ap.add_argument("--cpu-epochs", type=int, default=20)
+    ap.add_argument("--cpu-epochs", type=int, default=50)
     ap.add_argument("--hot", type=int, default=0)
     ap.add_argument("--flush", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)

@@ -619,6 +619,18 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
             c->inst.push_back(I);
         }
         if ((rc = dalloc(c, &c->d_insts, (int64_t)c->inst.size()))) return bail(rc);
+        // workgroup map: fixed waves per instance, or at most the device's
+        // resident workgroups (no more than 2048 threads per compute unit),
+        // and at least one per instance
+        {
+            int cus = device_cu_count();
+            if (cus <= 0) cus = 256;
+            const int block = o->threads_per_block > 0 ? o->threads_per_block : 512;
+            const int64_t bpi = o->waves > 0 ? ((int64_t)o->waves * 64 + block - 1) / block : 1;
+            c->map_cap = std::max<int64_t>({(int64_t)c->inst.size() * bpi, (int64_t)cus * (2048 / block),
+                                            (int64_t)c->inst.size()});
+            if ((rc = dalloc(c, &c->d_map, c->map_cap))) return bail(rc);
+        }
         if ((rc = step([&]() -> int {
                  HIPCHK(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
                  return ASAGA_OK;
@@ -723,14 +735,9 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     for (size_t k : act) S.hot = stable_hot(c, c->inst[k], S.hot, (double)blocks[k]);
     S.tier = std::min(S.tier, S.hot);
     *Sout = S;
-    if ((int64_t)n_blocks > c->map_cap) {
-        drop_graphs(c);
-        BlockMap* m = nullptr;
-        int rc = dalloc(c, &m, (int64_t)n_blocks);
-        if (rc) return rc;
-        c->d_map = m;
-        c->map_cap = n_blocks;
-    }
+    if ((int64_t)n_blocks > c->map_cap)
+        return fail(c, ASAGA_E_STATE, "batched launch needs " + std::to_string(n_blocks) +
+                                          " workgroups, more than the map allocated at initialisation");
     return ASAGA_OK;
 }
 
