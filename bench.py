@@ -70,6 +70,43 @@ def traffic_from_profile(per_launch_updates: int):
         return None
 
 
+def tau_sweep(p, dev_arrays, fstar, stream):
+    """Iterations to 1e-9 versus updates in flight, the device-side version
+    of the paper's speedup study: one fixed step (1/16 of the serial rule,
+    stable at every point here), wavefronts in flight from 64 to 2048; the
+    overlap tau of each point is measured by the sampled clock log of
+    asaga_overlap over its first two epochs."""
+    import numpy as np
+    import torch
+
+    import paper_1606_04809_amd as A
+
+    rule = 1.0 / (3.0 * (0.25 * float(np.max(np.add.reduceat(p.val ** 2, p.rowptr[:-1]))) + p.lam))
+    out = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for waves in (64, 128, 256, 512, 1024, 2048):
+        g = A.Solver(p.n, p.d, *dev_arrays, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC, seed=0, step=rule / 16,
+                     waves=waves, stream=stream)
+        r = g.overlap(2)
+        epochs, rel, secs = 2, (g.objective() - fstar) / fstar, 0.0
+        while rel > 1e-9 and epochs < 200:
+            e0.record(stream)
+            g.epochs(1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            secs += e0.elapsed_time(e1) / 1e3
+            epochs += 1
+            rel = (g.objective() - fstar) / fstar
+        g.close()
+        row = {"waves": waves, "tau_mean": r.tau_mean, "tau_p99": r.tau_p99, "tau_max": r.tau_max,
+               "latency_us": r.latency_mean_us, "little": r.little, "updates_per_s": r.updates_per_s,
+               "epochs_to_1e-9": epochs if rel <= 1e-9 else None, "final_rel": rel,
+               "seconds_to_1e-9": secs + 2 * p.n / r.updates_per_s if rel <= 1e-9 else None}
+        log(f"tau sweep: {row}")
+        out.append(row)
+    return {"step_over_serial_rule": 1.0 / 16, "points": out}
+
+
 def batched_leg(args, dev, stream):
     """The lambda path x folds workload (160 instances over the bfloat16
     config-2 matrix): all instances in one persistent kernel per epoch,
@@ -205,6 +242,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape and step instead of asaga_autotune's choice")
     ap.add_argument("--skip-batched", action="store_true", help="omit the batched lambda-path x folds leg")
+    ap.add_argument("--tau-sweep", action="store_true",
+                    help="add the overlap sweep: samples in flight (measured) and epochs to 1e-9 at a fixed step "
+                         "versus wavefronts in flight")
     ap.add_argument("--plain-instances", type=int, default=160,
                     help="instances of the batch also solved one by one with the plain FP64 kernel (spread "
                          "evenly over the 160)")
@@ -332,6 +372,7 @@ def main():
                "final_rel_subopt": rel}
         log(f"time to 1e-9: {tta}")
 
+    sweep = tau_sweep(p, dev_arrays, fstar, stream) if args.tau_sweep else None
     del dev_arrays
     batched = None if args.skip_batched else batched_leg(args, dev, stream)
 
@@ -375,6 +416,7 @@ def main():
         "time_to_1e-9": tta,
         "autotune": tune,
         "batched": batched,
+        "tau_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

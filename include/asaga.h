@@ -305,9 +305,10 @@ int asaga_widen(asaga_ctx* ctx);
  * to ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
  * (f is lambda-strongly convex).  Smaller steps are probed while the
  * estimate improves; a count whose probe alone would take longer than the
- * best estimate so far ends the search.  The best step of each of the three
- * best counts then runs 3 * probe_epochs epochs, and the rate over its last
- * third (closer to the asymptotic rate than the short probe's) decides; a
+ * best estimate so far ends the search.  The four best pairs (at most two
+ * steps per count) then run 3 * probe_epochs epochs each, and the rate over
+ * the last third (closer to the asymptotic rate than the short probe's)
+ * decides; a
  * run already certified at a checkpoint counts the epochs to the crossing,
  * interpolated on log ||grad f||^2.  With FP32 x (ASAGA_PREC_MIXED) a
  * gradient norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||)
@@ -315,7 +316,7 @@ int asaga_widen(asaga_ctx* ctx);
  * instability.  The best pair is kept, the state is reset to
  * x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair was
  * stable.
- * Batched contexts (opts.step must be 0): the hot-set size (4096 or 1024
+ * Batched contexts (opts.step and opts.waves must be 0): the hot-set size (4096 or 1024
  * columns) and the constant c of the step law of asaga_epochs are chosen
  * on the active instance with the smallest lambda (the slowest, the last
  * one running) alone on the device, by the same step ladder (with FP32 x,
@@ -326,6 +327,43 @@ int asaga_widen(asaga_ctx* ctx);
  * `waves` in the report is per instance with all active instances
  * running, `gamma` instance 0's step then. */
 int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);
+
+/* Overlap of the asynchronous updates: an estimate of the delay tau of
+ * Section 3 (Assumption 1: a read may miss the updates still in flight). */
+typedef struct asaga_overlap_report {
+    int64_t logged;          /* updates sampled (one in every `every`)                */
+    int64_t every;           /* sampling interval                                     */
+    double tau_mean;         /* updates in flight at a sampled update's read: mean,   */
+    double tau_p50;          /*   median,                                             */
+    double tau_p99;          /*   99th percentile                                     */
+    double tau_max;          /*   and largest (each a count of sampled updates in     */
+                             /*   flight times `every`)                               */
+    double latency_mean_us;  /* read to writes visible device-wide, mean              */
+    double latency_p99_us;   /*   and 99th percentile                                 */
+    double updates_per_s;    /* throughput over the sampled epochs                    */
+    double little;           /* updates_per_s * latency_mean: the mean in flight by   */
+                             /*   Little's law, a cross-check of tau_mean             */
+} asaga_overlap_report;
+
+/* Single-instance async contexts: apply n_epochs epochs (they count as
+ * ordinary epochs of the solve) while about one update in 1024, chosen by a
+ * hash of its sample counter (independently of which wavefront runs it and
+ * when), records the device clock at its read and once its global writes
+ * are visible device-wide, then estimate the overlap from those intervals
+ * with asaga_overlap_estimate.  Writes combined in a workgroup's LDS become
+ * visible at its next flush, later than this clock says: tau counts updates
+ * in flight, not that extra delay of hot columns. */
+int asaga_overlap(asaga_ctx* ctx, int64_t n_epochs, asaga_overlap_report* report);
+
+/* The estimator of asaga_overlap, on host memory (no device use): `log` holds
+ * n_logged (start, end) clock pairs (int64, start <= end) of updates sampled
+ * one in `every` from non-overlapping launches; clock_hz is the clock's rate,
+ * updates_per_s the throughput.  For each sampled update, the sampled
+ * updates that started before its start and end after it are in flight at
+ * its read; times `every` that estimates all updates in flight.  Pairs with
+ * start = 0 (not written) are skipped. */
+int asaga_overlap_estimate(const int64_t* log, int64_t n_logged, int64_t every, double clock_hz,
+                           double updates_per_s, asaga_overlap_report* report);
 
 /* Derived numbers (instance 0, plus launch shape). */
 int asaga_info_get(asaga_ctx* ctx, asaga_info* out);

@@ -86,6 +86,13 @@ class asaga_tune_report(ctypes.Structure):
                 ("est_epochs", ctypes.c_double), ("est_seconds", ctypes.c_double)]
 
 
+class asaga_overlap_report(ctypes.Structure):
+    _fields_ = [("logged", ctypes.c_int64), ("every", ctypes.c_int64), ("tau_mean", ctypes.c_double),
+                ("tau_p50", ctypes.c_double), ("tau_p99", ctypes.c_double), ("tau_max", ctypes.c_double),
+                ("latency_mean_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
+                ("updates_per_s", ctypes.c_double), ("little", ctypes.c_double)]
+
+
 class asaga_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("delta_r", ctypes.c_int64), ("t", ctypes.c_int64), ("L", ctypes.c_double),
@@ -113,6 +120,9 @@ _SIGS = {
     "asaga_reanchor": (ctypes.c_int, [_CTX]),
     "asaga_widen": (ctypes.c_int, [_CTX]),
     "asaga_autotune": (ctypes.c_int, [_CTX, ctypes.c_double, ctypes.c_int32, ctypes.POINTER(asaga_tune_report)]),
+    "asaga_overlap": (ctypes.c_int, [_CTX, ctypes.c_int64, ctypes.POINTER(asaga_overlap_report)]),
+    "asaga_overlap_estimate": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                              ctypes.POINTER(asaga_overlap_report)]),
     "asaga_info_get": (ctypes.c_int, [_CTX, ctypes.POINTER(asaga_info)]),
     "asaga_sync": (ctypes.c_int, [_CTX]),
     "asaga_sample_stream": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
@@ -232,6 +242,20 @@ def asaga_widen(ctx):
 def asaga_autotune(ctx, target: float = 1e-9, probe_epochs: int = 9) -> asaga_tune_report:
     rep = asaga_tune_report()
     _check(_lib.asaga_autotune(ctx, float(target), int(probe_epochs), ctypes.byref(rep)), ctx)
+    return rep
+
+
+def asaga_overlap(ctx, n_epochs: int = 1) -> asaga_overlap_report:
+    rep = asaga_overlap_report()
+    _check(_lib.asaga_overlap(ctx, int(n_epochs), ctypes.byref(rep)), ctx)
+    return rep
+
+
+def asaga_overlap_estimate(log, every: int, clock_hz: float, updates_per_s: float = 0.0) -> asaga_overlap_report:
+    a = np.ascontiguousarray(log, dtype=np.int64).reshape(-1, 2)
+    rep = asaga_overlap_report()
+    _check(_lib.asaga_overlap_estimate(a.ctypes.data, len(a), int(every), float(clock_hz), float(updates_per_s),
+                                       ctypes.byref(rep)))
     return rep
 
 
@@ -356,6 +380,9 @@ class Solver:
 
     def autotune(self, target: float = 1e-9, probe_epochs: int = 9) -> asaga_tune_report:
         return asaga_autotune(self.ctx, target, probe_epochs)
+
+    def overlap(self, n_epochs: int = 1) -> asaga_overlap_report:
+        return asaga_overlap(self.ctx, n_epochs)
 
     def info(self) -> asaga_info:
         return asaga_info_get(self.ctx)

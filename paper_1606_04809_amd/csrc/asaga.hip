@@ -90,6 +90,10 @@ struct asaga_ctx {
     double* tmp = nullptr;    // [n]
     double* vec1 = nullptr;   // [d]
     double* vec2 = nullptr;   // [d]
+    long long* d_tau = nullptr;  // single instance: overlap log of (start, end) tick pairs
+    unsigned long long* d_tau_count = nullptr;
+    int64_t tau_cap = 0;         // pairs d_tau holds: twice the expected number per epoch, plus 64
+    bool tau_on = false;         // asaga_overlap is logging
     double* part = nullptr;   // [kSumParts]
     double* scal = nullptr;   // [4]
     int* flag = nullptr;      // [1]
@@ -233,6 +237,9 @@ InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
     a.count = count;
     a.blocks = 0;
     a.reserved = 0;
+    a.tau_log = nullptr;
+    a.tau_count = nullptr;
+    a.tau_cap = 0;
     return a;
 }
 
@@ -644,6 +651,11 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
         if ((rc = setup_instance(c, c->inst[k], same))) return bail(rc);
     }
     pick_shape(c);
+    if (!bt) {
+        c->tau_cap = 2 * (c->n / (int64_t)kTauEvery) + 64;
+        if ((rc = dalloc(c, &c->d_tau, 2 * c->tau_cap))) return bail(rc);
+        if ((rc = dalloc(c, &c->d_tau_count, 1))) return bail(rc);
+    }
     if ((rc = step([&]() -> int {
              HIPCHK(c, hipStreamSynchronize(c->st));
              return ASAGA_OK;
@@ -839,7 +851,13 @@ int asaga_updates(asaga_ctx* c, int64_t count) {
     const int64_t piece = S.serial ? ((int64_t)1 << 18) : count;
     for (int64_t done = 0; done < count;) {
         const int64_t k = count - done < piece ? count - done : piece;
-        HIPCHK(c, launch_updates(mat(c), inst_args(I, (uint64_t)I.t, (uint64_t)k), S, c->flag, c->st));
+        InstArgs a = inst_args(I, (uint64_t)I.t, (uint64_t)k);
+        if (c->tau_on) {
+            a.tau_log = c->d_tau;
+            a.tau_count = c->d_tau_count;
+            a.tau_cap = (uint64_t)c->tau_cap;
+        }
+        HIPCHK(c, launch_updates(mat(c), a, S, c->flag, c->st));
         I.t += k;
         done += k;
     }
@@ -1080,6 +1098,8 @@ namespace {
 // ladder; then step_cap is checked with every instance running.
 int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune_report* rep) {
     if (c->o.step > 0.0) return fail(c, ASAGA_E_STATE, "batched autotuning chooses the steps: opts.step must be 0");
+    if (c->o.waves > 0)
+        return fail(c, ASAGA_E_STATE, "batched autotuning shares the device among the instances: opts.waves must be 0");
     const size_t ni = c->inst.size();
     std::vector<bool> was_active(ni);
     size_t cal = ni;
@@ -1370,20 +1390,19 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         }
         if (rc) break;
     }
-    // The short probes see mostly the fast early decrease; the three best
+    // The short probes see mostly the fast early decrease; the best
     // candidates run three times longer, and the rate over their last third
     // decides.
     if (!rc && stable_cands.size() > 1) {
         std::sort(stable_cands.begin(), stable_cands.end(),
                   [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });
-        // the best step of each wavefront count, then the three best counts
+        // the two best steps of each wavefront count, four candidates in all
         std::vector<Cand> fin;
         for (const Cand& k : stable_cands) {
-            bool seen = false;
-            for (const Cand& q : fin) seen = seen || q.S.waves == k.S.waves;
-            if (!seen) fin.push_back(k);
+            int seen = 0;
+            for (const Cand& q : fin) seen += q.S.waves == k.S.waves ? 1 : 0;
+            if (seen < 2 && fin.size() < 4) fin.push_back(k);
         }
-        fin.resize(std::min<size_t>(3, fin.size()));
         stable_cands = fin;
         const int cps3[3] = {probe_epochs, 2 * probe_epochs, 3 * probe_epochs};
         best = Cand{};
@@ -1425,6 +1444,104 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         rep->est_seconds = best.est_s;
     }
     return ASAGA_OK;
+}
+
+int asaga_overlap_estimate(const int64_t* log, int64_t n_logged, int64_t every, double clock_hz,
+                           double updates_per_s, asaga_overlap_report* out) {
+    if (!out || (n_logged > 0 && !log) || n_logged < 0 || every < 1 || !(clock_hz > 0.0))
+        return fail(nullptr, ASAGA_E_ARG, "bad overlap estimate arguments");
+    std::vector<int64_t> st, en;
+    for (int64_t i = 0; i < n_logged; ++i) {
+        const int64_t a = log[2 * i], b = log[2 * i + 1];
+        if (a == 0) continue;
+        if (b < a) return fail(nullptr, ASAGA_E_ARG, "overlap log pair ends before it starts");
+        st.push_back(a);
+        en.push_back(b);
+    }
+    *out = asaga_overlap_report{};
+    out->logged = (int64_t)st.size();
+    out->every = every;
+    out->updates_per_s = updates_per_s;
+    if (st.empty()) return ASAGA_OK;
+    std::vector<int64_t> ss = st, es = en;
+    std::sort(ss.begin(), ss.end());
+    std::sort(es.begin(), es.end());
+    std::vector<double> tau(st.size()), lat(st.size());
+    double tsum = 0.0, lsum = 0.0;
+    for (size_t i = 0; i < st.size(); ++i) {
+        // started strictly before st[i], minus those already ended by then:
+        // an interval that ended by st[i] also started before it
+        const int64_t started = std::lower_bound(ss.begin(), ss.end(), st[i]) - ss.begin();
+        const int64_t ended = std::upper_bound(es.begin(), es.end(), st[i]) - es.begin();
+        tau[i] = (double)std::max<int64_t>(0, started - ended) * (double)every;
+        lat[i] = (double)(en[i] - st[i]) / clock_hz * 1e6;
+        tsum += tau[i];
+        lsum += lat[i];
+    }
+    auto pct = [](std::vector<double> v, double q) {
+        std::sort(v.begin(), v.end());
+        return v[(size_t)std::min<double>((double)v.size() - 1, std::floor(q * (double)(v.size() - 1) + 0.5))];
+    };
+    out->tau_mean = tsum / (double)st.size();
+    out->tau_p50 = pct(tau, 0.5);
+    out->tau_p99 = pct(tau, 0.99);
+    out->tau_max = *std::max_element(tau.begin(), tau.end());
+    out->latency_mean_us = lsum / (double)st.size();
+    out->latency_p99_us = pct(lat, 0.99);
+    out->little = updates_per_s * out->latency_mean_us * 1e-6;
+    return ASAGA_OK;
+}
+
+int asaga_overlap(asaga_ctx* c, int64_t n_epochs, asaga_overlap_report* out) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!out || n_epochs < 1) return fail(c, ASAGA_E_ARG, "need a report and n_epochs >= 1");
+    if (c->d_insts || c->shape.serial || !c->d_tau)
+        return fail(c, ASAGA_E_STATE, "overlap logging needs a single-instance async context");
+    const Inst& I = c->inst[0];
+    int dev = 0, khz = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(c, ASAGA_E_HIP, "the device reports no wall-clock rate");
+    std::vector<int64_t> all;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    double secs = 0.0;
+    int rc = ASAGA_OK;
+    for (int64_t e = 0; e < n_epochs && !rc; ++e) {
+        hipError_t he = launch_fill_i64(c->d_tau, 0, 2 * c->tau_cap, c->st);
+        if (he == hipSuccess)
+            he = launch_fill_i64(reinterpret_cast<long long*>(c->d_tau_count), 0, 1, c->st);
+        if (he == hipSuccess) he = hipEventRecord(e0, c->st);
+        if (he != hipSuccess) {
+            rc = fail(c, ASAGA_E_HIP, std::string("overlap: ") + hipGetErrorString(he));
+            break;
+        }
+        c->tau_on = true;
+        rc = asaga_updates(c, I.m);
+        c->tau_on = false;
+        if (rc) break;
+        he = hipEventRecord(e1, c->st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        unsigned long long used = 0;
+        if (he == hipSuccess) he = hipMemcpy(&used, c->d_tau_count, 8, hipMemcpyDeviceToHost);
+        const int64_t pairs = std::min<int64_t>((int64_t)used, c->tau_cap);
+        const size_t at = all.size();
+        all.resize(at + 2 * (size_t)pairs);
+        if (he == hipSuccess && pairs > 0)
+            he = hipMemcpy(all.data() + at, c->d_tau, (size_t)pairs * 16, hipMemcpyDeviceToHost);
+        if (he != hipSuccess) rc = fail(c, ASAGA_E_HIP, std::string("overlap: ") + hipGetErrorString(he));
+        secs += ms * 1e-3;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = asaga_overlap_estimate(all.data(), (int64_t)all.size() / 2, (int64_t)kTauEvery, (double)khz * 1e3,
+                                secs > 0.0 ? (double)(n_epochs * I.m) / secs : 0.0, out);
+    if (rc) return fail(c, rc, asaga_last_error(nullptr));
+    return check_flag(c);
 }
 
 int asaga_info_get(asaga_ctx* c, asaga_info* out) {

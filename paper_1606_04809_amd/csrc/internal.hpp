@@ -30,7 +30,16 @@ struct InstArgs {
     uint64_t count;       // updates this launch applies to the instance (0: skip it)
     int32_t blocks;       // batched: workgroups serving the instance
     int32_t reserved;
+    // overlap log (nullptr: off): a sample whose counter hashes to 0 modulo
+    // kTauEvery (an independent thinning, unrelated to which lane group or
+    // round runs it) takes the next entry e = (*tau_count)++ below tau_cap and
+    // writes its read-start and writes-visible clock ticks to tau_log[2e],
+    // tau_log[2e + 1]
+    long long* tau_log;
+    unsigned long long* tau_count;
+    uint64_t tau_cap;
 };
+constexpr uint64_t kTauEvery = 1024;
 
 // Batched launches: workgroup b serves instance inst, as its rank-th
 // workgroup (inst < 0: idle).
@@ -90,6 +99,7 @@ size_t update_lds_bytes(const UpdateShape& S);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, int64_t stride, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
+hipError_t launch_fill_i64(long long* p, long long v, int64_t count, hipStream_t st);
 // cnt_c += #{j < m : c in S_rows[j]}; hot_first: the most-used columns are the
 // lowest indices (after relabelling)
 hipError_t launch_colcount(const MatArgs& A, const int32_t* rows, int64_t m, int32_t* cnt, bool hot_first,

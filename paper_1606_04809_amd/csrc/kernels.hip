@@ -359,7 +359,25 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
             const uint64_t s2 = s + slots;
             RowRef nxt{0, 0, 0, 0, 0.0, 0.0};
             if (s2 < I.count) nxt = row_ref<SERIAL, MIXED>(A, I, t0 + s2);
+            // sampled overlap log: clock at the read, and once the sample's
+            // global writes are visible device-wide
+            const bool logged = I.tau_log != nullptr && s < I.count &&
+                                splitmix64(0x7A05EEDull, t0 + s) % kTauEvery == 0;
+            long long t_read = 0;
+            if (logged) t_read = wall_clock64();
             if (s < I.count) apply_update<G, P, SERIAL, RACY, MIXED, VT>(A, I, cur, gl, hot, flag);
+            if (logged) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const long long t_done = wall_clock64();
+                if (gl == 0) {
+                    const unsigned long long e = __hip_atomic_fetch_add(I.tau_count, 1ull, __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+                    if (e < I.tau_cap) {
+                        I.tau_log[2 * e] = t_read;
+                        I.tau_log[2 * e + 1] = t_done;
+                    }
+                }
+            }
             cur = nxt;
         }
         if (hot > 0) {
@@ -556,6 +574,11 @@ __global__ void k_fill(T* p, T v, int64_t count, int64_t stride) {
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     k_fill<int32_t><<<grid_for(count, 256), 256, 0, st>>>(p, v, count, 1);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i64(long long* p, long long v, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    k_fill<long long><<<grid_for(count, 256), 256, 0, st>>>(p, v, count, 1);
     return hipGetLastError();
 }
 hipError_t launch_fill_f64(double* p, double v, int64_t count, int64_t stride, hipStream_t st) {

@@ -116,3 +116,50 @@ def test_null_context_calls_fail_cleanly():
     assert lib.asaga_set_active(None, None) == A.ASAGA_E_ARG
     lib.asaga_free.argtypes = [ctypes.c_void_p]
     lib.asaga_free(None)
+
+
+def test_overlap_estimator_small_exact_case():
+    # intervals [0,10], [5,15], [12,20] ticks at 1 tick per microsecond, every update logged:
+    # at 5 one update is in flight ([0,10]); at 12 one ([5,15]); at 0 none
+    log = np.array([[0 + 1, 10 + 1], [5 + 1, 15 + 1], [12 + 1, 20 + 1]])  # shifted: start 0 marks "not written"
+    r = A.asaga_overlap_estimate(log, every=1, clock_hz=1e6, updates_per_s=1e5)
+    assert r.logged == 3 and r.every == 1
+    assert r.tau_max == 1.0 and r.tau_mean == pytest.approx(2.0 / 3.0)
+    assert r.latency_mean_us == pytest.approx((10 + 10 + 8) / 3.0)
+    assert r.little == pytest.approx(1e5 * r.latency_mean_us * 1e-6)
+
+
+def test_overlap_estimator_recovers_workers_in_flight():
+    # W workers run back-to-back updates of random length; one update in
+    # `every` (in start order) is logged.  At any instant every other worker
+    # has one update in flight, so the estimate is W - 1 on average.
+    rng = np.random.default_rng(3)
+    W, per, every = 64, 400, 8
+    starts, ends = [], []
+    for w in range(W):
+        t = rng.uniform(0, 50)
+        for _ in range(per):
+            d = rng.uniform(20, 80)
+            starts.append(t)
+            ends.append(t + d)
+            t += d
+    order = np.argsort(starts)
+    st = (np.asarray(starts)[order] * 1000).astype(np.int64) + 1
+    en = (np.asarray(ends)[order] * 1000).astype(np.int64) + 1
+    keep = (np.arange(len(st)) % every == 0) & (st > 100_000) & (en < st.max() - 100_000)  # steady state
+    log = np.stack([st[keep], en[keep]], axis=1)
+    r = A.asaga_overlap_estimate(log, every=every, clock_hz=1e9, updates_per_s=0.0)
+    assert abs(r.tau_mean - (W - 1)) < 0.1 * W, r.tau_mean
+    assert r.tau_p50 <= r.tau_p99 <= r.tau_max
+    assert r.latency_mean_us == pytest.approx(50.0, rel=0.05)   # U(20, 80) units of 1000 ticks at 1 GHz
+
+
+def test_overlap_estimator_rejects_bad_input():
+    with pytest.raises(A.AsagaError):
+        A.asaga_overlap_estimate(np.array([[10, 5]]), every=1, clock_hz=1.0)
+    with pytest.raises(A.AsagaError):
+        A.asaga_overlap_estimate(np.array([[1, 5]]), every=0, clock_hz=1.0)
+    with pytest.raises(A.AsagaError):
+        A.asaga_overlap_estimate(np.array([[1, 5]]), every=1, clock_hz=0.0)
+    r = A.asaga_overlap_estimate(np.zeros((4, 2), dtype=np.int64), every=1, clock_hz=1.0)
+    assert r.logged == 0

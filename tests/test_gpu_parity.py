@@ -427,6 +427,31 @@ def test_mixed_precision_reaches_1e9():
         assert err < 1e-6
 
 
+def test_overlap_log_counts_samples_in_flight():
+    """The sampled overlap log of asaga_overlap: the updates in flight at a
+    read grow with the wavefronts in flight, match Little's law
+    (throughput x latency), and the logged epochs count as epochs of the
+    solve."""
+    p = datagen.config2(n=100_000, d=20_000)
+    taus = {}
+    # about one update in 1024 is logged (~390 over 4 epochs); the estimate counts
+    # logged updates in flight, about 30 events at 128 wavefronts and 250 at
+    # 1024, hence the wider tolerance at 128
+    for waves, tol in ((128, 3.0), (1024, 1.6)):
+        with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=waves) as g:
+            assert g.info().lanes_per_sample == 64       # one sample per wavefront
+            r = g.overlap(4)
+            say(f"waves {waves}: logged {r.logged}, tau mean {r.tau_mean:.0f} p99 {r.tau_p99:.0f} "
+                f"max {r.tau_max:.0f}, latency {r.latency_mean_us:.2f} us, Little {r.little:.0f}, "
+                f"{r.updates_per_s / 1e6:.0f} M updates/s")
+            assert abs(r.logged - 4 * p.n / 1024) < 6 * np.sqrt(4 * p.n / 1024) and r.every == 1024
+            assert r.tau_mean <= 1.5 * waves
+            assert 1.0 / tol <= r.tau_mean / r.little <= tol
+            assert g.info().t == 4 * p.n
+            taus[waves] = r.tau_mean
+    assert taus[1024] > 4 * taus[128]
+
+
 def test_racy_updates_lose_information():
     # Appendix G: without atomic additions concurrent updates overwrite each
     # other; the lost abar increments show up as a broken running average
