@@ -36,9 +36,10 @@
  *
  * Step size: when opts.step <= 0, gamma = min(1/(3L), 1/(lambda max_v D_v))
  * with L = c max_i ||a_i||^2 + lambda, c = 1/4 (logistic) or 1 (squared);
- * in ASAGA_MODE_ASYNC that value is divided by 4.  With many samples in
+ * in ASAGA_MODE_ASYNC that value is multiplied by min(1, 512 / G), G the
+ * samples in flight (lane groups of the launch).  With many samples in
  * flight, updates read state that is older by up to tau samples (Section
- * 3.3, Assumption 1), and the stable step shrinks as tau grows along the
+ * 3.3, Assumption 1), and the stable step shrinks like 1/tau along the
  * directions many rows share (Theorem 2); asaga_autotune measures the step
  * and launch shape that reach a target accuracy soonest.
  *
@@ -126,9 +127,9 @@ typedef struct asaga_opts {
     uint64_t seed;            /* sample-stream seed                                */
     int32_t mode;             /* ASAGA_MODE_*                                      */
     int32_t precision;        /* ASAGA_PREC_*                                      */
-    int32_t waves;            /* async: wavefronts in flight (0 = automatic: 8
-                                 per compute unit, and at most n/64 samples in
-                                 flight).  Batches: wavefronts per
+    int32_t waves;            /* async: wavefronts in flight (0 = automatic: one
+                                 workgroup per compute unit, and at most n/64
+                                 samples in flight).  Batches: wavefronts per
                                  instance, fixed; 0 shares the device's
                                  resident workgroups equally among the
                                  instances still active (see asaga_epochs)       */
@@ -150,7 +151,11 @@ typedef struct asaga_opts {
                                  two flushes of those combined writes
                                  (0 = automatic)                                  */
     int32_t threads_per_block;/* async: workgroup size, a multiple of 64 up to
-                                 512 (0 = automatic)                              */
+                                 1024 (0 = automatic: 512).  A workgroup shares
+                                 one hot set, so larger ones need fewer flush
+                                 requests per sample, but one workgroup per
+                                 compute unit then puts more samples in
+                                 flight, which lowers the stable step          */
     int32_t hot_tier_columns; /* async: the first hot columns, flushed after every
                                  round of flush_every samples; the others are
                                  flushed every hot_tier_every rounds
@@ -235,8 +240,7 @@ int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_o
  *     gamma_k = rule_k * min(cap, c / G_k),
  * G_k the lane groups (samples in flight) serving it: the stable step
  * shrinks with the delay (Theorem 2).  c and cap come from asaga_autotune;
- * before it, c gives a single instance at 8 wavefronts per compute unit a
- * quarter of its rule, and cap = 1.  The n_epochs launches are captured once
+ * before it, c = 512 (the single-instance default) and cap = 1.  The n_epochs launches are captured once
  * per distinct n_epochs (up to 64; larger counts run in pieces) into a
  * hipGraph on a private stream and replayed on the context's stream (unless
  * opts.plain_launch).  It waits for the previous call's work before
@@ -294,18 +298,21 @@ int asaga_widen(asaga_ctx* ctx);
  * the other shape parameters stay as the context has them, except as said
  * for batches below).
  * Fewer samples in flight tolerate a larger step (Theorem 2) but take longer
- * per epoch, so wavefront counts are tried from 8 per compute unit (at most
- * n/64 samples in flight) down to 1/8 per compute unit, halving.  For each
- * count it times one epoch, then, for steps from the serial rule downwards
- * by halves (to 1/64 of it), runs
- * `probe_epochs` epochs from x = 0, measures the decay rate of ||grad f||
- * (FP64 full gradients at three checkpoints; a step whose squared gradient
- * norm more than doubles between checkpoints, or does not decrease from the
- * first to the last, is rejected as unstable) and extrapolates
- * to ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
+ * per epoch, so wavefront counts are tried from one workgroup per compute
+ * unit (at most n/64 samples in flight) down to 1/8 wavefront per compute
+ * unit, halving.  For each count it times one epoch, then, for steps from
+ * the serial rule downwards by factors of 2^(1/3) (to 1/64 of it), runs
+ * `probe_epochs` epochs from x = 0 with FP64 objectives and full gradients
+ * at three equally spaced checkpoints (a step whose gradient norm does not
+ * fall, or whose objective rises, between checkpoints is rejected as
+ * unstable, unless the run is already certified), and estimates the epochs to
+ * (f - f*)/f* <= `target` by Aitken's extrapolation of the objective (f* and
+ * the contraction per epoch from the three values); where the objective
+ * gives no estimate, it extrapolates the gradient norm's decay to
+ * ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
  * (f is lambda-strongly convex).  Smaller steps are probed while the
  * estimate improves; a count whose probe alone would take longer than the
- * best estimate so far ends the search.  The four best pairs (at most two
+ * best estimate so far ends the search.  The six best pairs (at most two
  * steps per count) then run 3 * probe_epochs epochs each, and the rate over
  * the last third (closer to the asymptotic rate than the short probe's)
  * decides; a
@@ -323,7 +330,10 @@ int asaga_widen(asaga_ctx* ctx);
  * whose rounding floor is reached within a short probe, the largest stable
  * step); then cap is
  * the largest of 1, 1/2, 1/4, 1/8 with which no active instance is
- * unstable in that sense with all of them running.
+ * unstable with all of them running, where among many instances unstable
+ * means a squared gradient norm that more than doubles between checkpoints
+ * or does not decrease from the first to the last (single checkpoints
+ * without decrease are noise of the asynchronous updates).
  * `waves` in the report is per instance with all active instances
  * running, `gamma` instance 0's step then. */
 int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);

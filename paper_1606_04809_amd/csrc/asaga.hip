@@ -23,8 +23,18 @@ thread_local std::string g_init_error = "no error";
 
 constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
 constexpr int kMaxHot = 4096;    // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
-constexpr int kMaxBlock = 512;   // the update kernels are compiled for at most 512 threads per workgroup
-constexpr double kAsyncStepFactor = 0.25;
+constexpr int kMaxBlock = 1024;  // the update kernels are compiled for at most 1024 threads per workgroup
+// Default workgroup: 512 threads.  1024-thread workgroups share one hot set
+// among twice the samples (fewer flush requests per sample: 400 vs 267 M
+// updates/s on the RCV1-shaped instance at one workgroup per compute unit)
+// but double the samples in flight, which halves the stable step; on
+// instances whose convergence is step-limited (small lambda) that costs
+// more epochs than it saves time, so the larger workgroup is an option.
+// Default asynchronous step: rule * min(1, kStepGroups / G) with G the lane
+// groups (samples) in flight.  The stable step falls like 1/G (Theorem 2);
+// on the RCV1-shaped instance the edge is near 700 / G (2048 in flight:
+// stable at 0.35, 4096: at 0.15, not at 0.19), and 512 / G leaves a margin.
+constexpr double kStepGroups = 512.0;
 constexpr int64_t kMaxGraphEpochs = 64;  // epochs captured in one hipGraph
 
 struct Inst {
@@ -203,7 +213,7 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->hot_tier_every < 0 || o->hot_tier_every > (1 << 16))
         return fail(nullptr, ASAGA_E_ARG, "hot_tier_every out of range");
     if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
-        return fail(nullptr, ASAGA_E_ARG, "threads_per_block must be 0 or a multiple of 64 up to 512");
+        return fail(nullptr, ASAGA_E_ARG, "threads_per_block must be 0 or a multiple of 64 up to 1024");
     if (o->plain_launch != 0 && o->plain_launch != 1) return fail(nullptr, ASAGA_E_ARG, "plain_launch must be 0 or 1");
     if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
     return ASAGA_OK;
@@ -330,11 +340,8 @@ int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
         double g = 1.0 / (3.0 * I.L);
         if (I.lambda * dmax > 0.0 && 1.0 / (I.lambda * dmax) < g) g = 1.0 / (I.lambda * dmax);
         I.rule = g;
-        // Asynchronous updates read state that is older by the number of
-        // samples in flight; the stable step shrinks with that delay
-        // (Theorem 2).  A quarter of the serial rule is the default for the
-        // default launch shape; asaga_autotune measures it per problem.
-        if (c->o.mode == ASAGA_MODE_ASYNC) g *= kAsyncStepFactor;
+        // asynchronous: scaled to the samples in flight once the launch
+        // shape is known (default_async_steps)
         I.gamma = g;
     }
     return zero_state(c, I);
@@ -390,6 +397,16 @@ int tier_every_for(const asaga_ctx* c, const UpdateShape& S) {
     return tier_every_from(c, gl * (double)S.waves * (64.0 / (double)S.lanes));
 }
 
+// lane groups (samples) in flight of a single-instance launch shape
+double groups_in_flight(const UpdateShape& S) { return (double)S.waves * (64.0 / (double)S.lanes); }
+
+// Without opts.step, an asynchronous single instance starts from
+// rule * min(1, kStepGroups / G); batches get theirs per launch.
+void default_async_steps(asaga_ctx* c) {
+    if (c->o.step > 0.0 || c->shape.serial || c->d_insts) return;
+    for (Inst& I : c->inst) I.gamma = I.rule * std::min(1.0, kStepGroups / groups_in_flight(c->shape));
+}
+
 void pick_shape(asaga_ctx* c) {
     UpdateShape& S = c->shape;
     S.serial = c->o.mode == ASAGA_MODE_SERIAL;
@@ -419,11 +436,12 @@ void pick_shape(asaga_ctx* c) {
     if (waves == 0) {
         int cus = device_cu_count();
         if (cus <= 0) cus = 256;
-        // one instance: 8 wavefronts per compute unit, within the bound on
-        // samples in flight; a batch: planned per launch (64 per instance is
-        // only reported until then)
+        // one instance: one 16-wavefront workgroup per compute unit, within
+        // the bound on samples in flight; a batch: planned per launch (64 per
+        // instance is only reported until then)
         waves = c->d_insts ? 64
-                           : (int)std::min<int64_t>(cus * 8, std::max<int64_t>(1, max_groups_for(c->n) * lanes / 64));
+                           : (int)std::min<int64_t>(cus * (S.block / 64),
+                                                    std::max<int64_t>(1, max_groups_for(c->n) * lanes / 64));
     }
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
@@ -651,6 +669,7 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
         if ((rc = setup_instance(c, c->inst[k], same))) return bail(rc);
     }
     pick_shape(c);
+    default_async_steps(c);
     if (!bt) {
         c->tau_cap = 2 * (c->n / (int64_t)kTauEvery) + 64;
         if ((rc = dalloc(c, &c->d_tau, 2 * c->tau_cap))) return bail(rc);
@@ -726,12 +745,7 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
         for (size_t k : act)
             for (int r = 0; r < blocks[k]; ++r) map[b++] = BlockMap{(int32_t)k, r};
     }
-    double sg = c->step_groups;
-    if (sg <= 0.0) {
-        int cus = device_cu_count();
-        if (cus <= 0) cus = 256;
-        sg = kAsyncStepFactor * (double)cus * 8.0 * (64.0 / (double)S.lanes);
-    }
+    const double sg = c->step_groups > 0.0 ? c->step_groups : kStepGroups;
     double glg = 0.0;
     std::vector<InstArgs>& h = c->plan_h;
     h.resize(ni);
@@ -1067,6 +1081,25 @@ double probe_rate(const double* g2, const int* cps) {
     return r > 0.0 ? r : 0.0;
 }
 
+// Epochs until (f - f*)/f* <= target, from the objective at three equally
+// spaced checkpoints: the differences of a linearly converging sequence
+// shrink geometrically, so Aitken's extrapolation estimates f* and the
+// contraction per epoch.  Returns the checkpoint epoch if the last
+// difference is already below the target, and a negative value if the
+// differences do not shrink (no estimate).
+double aitken_epochs(const double* f, const int* cps, double target) {
+    const double d1 = f[1] - f[0], d2 = f[2] - f[1];
+    if (std::fabs(d2) <= target * std::fabs(f[2])) return (double)cps[2];
+    if (!(d1 < 0.0 && d2 < 0.0)) return -1.0;
+    const double r = d2 / d1;
+    if (!(r > 0.0 && r < 1.0)) return -1.0;
+    const double fstar = f[2] - d2 * d2 / (d2 - d1);
+    const double gap = f[2] - fstar;
+    if (!(gap > 0.0) || gap <= target * std::fabs(fstar)) return (double)cps[2];
+    const double per_epoch = std::log(r) / (double)(cps[2] - cps[1]);  // log contraction per epoch (< 0)
+    return (double)cps[2] + std::log(target * std::fabs(fstar) / gap) / per_epoch;
+}
+
 // ||grad f||^2 an autotuning probe accepts as converged: the strong-convexity
 // certificate of relative suboptimality `target`, or, with FP32 x, the floor
 // its rounding leaves (a gradient error of about 8 * 2^-24 * L * ||x||).
@@ -1160,6 +1193,11 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         for (size_t j = 0; j < ni; ++j) {
             if (!c->inst[j].active || reached[j] >= 0) continue;
             const double* gj = &g2[3 * j];
+            const double ea = aitken_epochs(&f[3 * j], cps, target);
+            if (ea >= 0.0) {
+                e = std::max(e, ea);
+                continue;
+            }
             const double r = probe_rate(gj, cps);
             if (r == 0.0) return false;
             e = std::max(e, (double)cps[2] + (gj[2] > goal[j] ? 0.5 * std::log(gj[2] / goal[j]) / r : 0.0));
@@ -1178,7 +1216,8 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         const int hot = (int)std::min<int64_t>(h, c->d);
         if (std::find(hots.begin(), hots.end(), hot) == hots.end()) hots.push_back(hot);
     }
-    const double scales[] = {1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625};
+    std::vector<double> scales;
+    for (int k = 0; k <= 18; ++k) scales.push_back(std::exp2(-(double)k / 3.0));
     for (int hot : hots) {
         UpdateShape S = base;
         S.hot = hot;
@@ -1285,7 +1324,7 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     if (c->d_insts) return autotune_batched(c, target, probe_epochs, rep);
     Inst& I = c->inst[0];
     const UpdateShape base = c->shape;
-    const double serial_rule = c->o.step > 0.0 ? c->o.step : I.gamma / kAsyncStepFactor;
+    const double serial_rule = c->o.step > 0.0 ? c->o.step : I.rule;
     int cus = device_cu_count();
     if (cus <= 0) cus = 256;
     const int wpb = base.block / 64;
@@ -1293,14 +1332,16 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     // wavefront counts from the fastest epoch (most samples in flight) to the
     // slowest; fewer samples in flight tolerate a larger step (Theorem 2)
     std::vector<UpdateShape> shapes;
-    const int wmax = (int)std::min<int64_t>(cus * 8, std::max<int64_t>(1, max_groups_for(I.m) * base.lanes / 64));
+    const int wmax = (int)std::min<int64_t>(cus * wpb, std::max<int64_t>(1, max_groups_for(I.m) * base.lanes / 64));
     for (int w = wmax; w >= std::max(wpb, std::min(wmax, cus / 8)); w /= 2) {
         UpdateShape S = base;
         S.waves = round_waves(w);
         if (!shapes.empty() && shapes.back().waves == S.waves) continue;
         shapes.push_back(S);
     }
-    const double scales[] = {1.0, 0.5, 0.25, 0.125, 0.0625, 0.03125, 0.015625};
+    // steps from the serial rule down to 1/64 of it, three per halving
+    std::vector<double> scales;
+    for (int k = 0; k <= 18; ++k) scales.push_back(std::exp2(-(double)k / 3.0));
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -1333,7 +1374,10 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
                              (double)(cps[k] - cps[k - 1]) * std::log(g2[k - 1] / goal_k) / std::log(g2[k - 1] / g2[k]);
                 return true;
             }
-            if (probe_unstable(g2, k)) return false;
+            // one instance: the gradient norm must fall and the objective
+            // must not rise at every checkpoint (slow instabilities pass a
+            // looser test within a short probe)
+            if (k > 0 && !(g2[k] < g2[k - 1] && f[k] <= f[k - 1])) return false;
         }
         int flag = 0;
         const hipError_t he = hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost);
@@ -1342,6 +1386,13 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             return false;
         }
         if (flag) return false;
+        // ranked on the objective (Aitken), which the target is about; the
+        // gradient-norm rate only when the objective gives no estimate
+        const double ea = aitken_epochs(f, cps, target);
+        if (ea >= 0.0) {
+            *est_e = ea;
+            return true;
+        }
         const double r = probe_rate(g2, cps);
         if (r == 0.0) return false;
         const double goal = probe_goal(c, I, target, f[2], x2);
@@ -1396,12 +1447,12 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     if (!rc && stable_cands.size() > 1) {
         std::sort(stable_cands.begin(), stable_cands.end(),
                   [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });
-        // the two best steps of each wavefront count, four candidates in all
+        // the two best steps of each wavefront count, six candidates in all
         std::vector<Cand> fin;
         for (const Cand& k : stable_cands) {
             int seen = 0;
             for (const Cand& q : fin) seen += q.S.waves == k.S.waves ? 1 : 0;
-            if (seen < 2 && fin.size() < 4) fin.push_back(k);
+            if (seen < 2 && fin.size() < 6) fin.push_back(k);
         }
         stable_cands = fin;
         const int cps3[3] = {probe_epochs, 2 * probe_epochs, 3 * probe_epochs};
@@ -1426,7 +1477,7 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     }
     if (!std::isfinite(best.est_s)) {
         c->shape = base;
-        I.gamma = serial_rule * kAsyncStepFactor;
+        I.gamma = c->o.step > 0.0 ? c->o.step : I.rule * std::min(1.0, kStepGroups / groups_in_flight(base));
         reset_state(c);
         return fail(c, ASAGA_E_DIVERGED, "no probed launch shape and step reduced the gradient norm steadily");
     }

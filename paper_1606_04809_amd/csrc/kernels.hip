@@ -393,7 +393,7 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
 constexpr int kPasses = 4;
 
 template <int G, bool SERIAL, bool RACY, bool MIXED, typename VT>
-__global__ void __launch_bounds__(512) k_update(MatArgs A, InstArgs I, HotArgs H, int* flag) {
+__global__ void __launch_bounds__(1024) k_update(MatArgs A, InstArgs I, HotArgs H, int* flag) {
     const uint64_t groups = blockDim.x / G;
     const uint64_t slot = blockIdx.x * groups + threadIdx.x / G;
     const uint64_t slots = (uint64_t)gridDim.x * groups;
@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(512) k_update(MatArgs A, InstArgs I, HotArgs H
 // Many instances in one persistent grid: the block map says which instance
 // each workgroup serves and as which of that instance's workgroups.
 template <int G, bool MIXED, typename VT>
-__global__ void __launch_bounds__(512) k_update_batched(MatArgs A, const InstArgs* insts, const BlockMap* map,
+__global__ void __launch_bounds__(1024) k_update_batched(MatArgs A, const InstArgs* insts, const BlockMap* map,
                                                         uint64_t epoch, HotArgs H, int* flag) {
     const BlockMap bm = map[blockIdx.x];
     if (bm.inst < 0) return;

@@ -103,7 +103,7 @@ def test_bad_arguments_are_rejected():
     expect(E, flush_every=-1)
     expect(E, threads_per_block=100)
     expect(E, threads_per_block=2048)
-    expect(E, threads_per_block=1024)
+    expect(E, threads_per_block=1088)
     expect(E, plain_launch=2)
     expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
 
