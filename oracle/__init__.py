@@ -54,6 +54,10 @@ _SIGS = {
     "oracle_objective": (_D, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P]),
     "oracle_gradient": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P, _P]),
     "oracle_memory_average": (_I, [_I64, _I64, _P, _P, _P, _P, _P]),
+    "oracle_svrg_full_gradient_due": (_I, [_U64, _U64, _I64]),
+    "oracle_svrg_snapshot": (None, [_I64, _I64, _P, _P, _P, _P, _I, _P, _P, _P]),
+    "oracle_svrg_indices": (_I, [_P, _P, _P, _P, _I, _D, _P, _D, _I64, _P, _I64, _P, _P, _P]),
+    "oracle_svrg_run": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P, _D, _U64, _U64, _I64, _P, _P, _P]),
 }
 
 
@@ -212,6 +216,47 @@ class SparseSaga:
         f = self.objective(x)
         g = self.gradient(x)
         return f, f - float(g @ g) / (2.0 * self.lam)
+
+
+class SparseSvrg(SparseSaga):
+    """Serial FP64 sparse SVRG with randomly timed full gradients (the
+    Appendix C variant): the memory (alpha_i = phi'(a_i . x~), abar its
+    average) is the snapshot's and changes only at snapshots; a snapshot is
+    taken at x0 and wherever the U stream fires (probability 1/n per
+    iteration)."""
+
+    def __init__(self, prob, step: float | None = None, seed: int = 0, lib=None):
+        super().__init__(prob, step=step, seed=seed, lib=lib)
+        self.snapshot()
+
+    def snapshot(self, state: State | None = None) -> State:
+        s = self.state if state is None else state
+        self.lib.oracle_svrg_snapshot(self.n, self.d, _p(self.rowptr), _p(self.colidx), _p(self.val), _p(self.b),
+                                      self.loss, _p(s.x), _p(s.alpha), _p(s.abar))
+        return s
+
+    def full_gradient_due(self, t: int) -> bool:
+        return bool(self.lib.oracle_svrg_full_gradient_due(self.seed, int(t), self.n))
+
+    def run(self, updates: int, state: State | None = None) -> State:
+        s = self.state if state is None else state
+        rc = self.lib.oracle_svrg_run(self.n, self.d, _p(self.rowptr), _p(self.colidx), _p(self.val), _p(self.b),
+                                      self.loss, self.lam, _p(self.D), self.gamma, self.seed, s.t, int(updates),
+                                      _p(s.x), _p(s.alpha), _p(s.abar))
+        if rc != 0:
+            raise RuntimeError(f"oracle_svrg_run failed ({rc})")
+        s.t += int(updates)
+        return s
+
+    def run_indices(self, idx, state: State | None = None) -> State:
+        s = self.state if state is None else state
+        idx = _c(idx, np.int64)
+        rc = self.lib.oracle_svrg_indices(_p(self.rowptr), _p(self.colidx), _p(self.val), _p(self.b), self.loss,
+                                          self.lam, _p(self.D), self.gamma, self.n, _p(idx), len(idx), _p(s.x),
+                                          _p(s.alpha), _p(s.abar))
+        if rc != 0:
+            raise RuntimeError(f"oracle_svrg_indices failed ({rc})")
+        return s
 
 
 # ---------------------------------------------------------------------------

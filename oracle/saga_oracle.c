@@ -170,6 +170,86 @@ int oracle_saga_run(int64_t n, const int64_t* rowptr, const int32_t* colidx, con
 }
 
 /* ------------------------------------------------------------------ */
+/* Sparse SVRG with randomly timed full gradients (Appendix C)         */
+/* ------------------------------------------------------------------ */
+
+/* The SVRG variant the paper extends its analysis to (Appendix C,
+ * "Extension to SVRG"): at the start of every iteration a binary U with
+ * P(U = 1) = 1/n decides whether a full gradient is computed at the current
+ * point (the snapshot x~) or an inner step is made.  For linear models the
+ * snapshot's per-sample gradients are the scalars alpha_i = phi'(a_i . x~)
+ * and its full gradient's data part is abar = (1/n) sum_i alpha_i a_i; the
+ * sparse inner step (the Sparse SVRG that Section 2 builds Sparse SAGA from)
+ * is
+ *     x+ = x - gamma ((phi'(a_i . x) - alpha_i) a_i + D_i (abar + lambda x)),
+ * i.e. Eq. SparseSAGA with the memory held at the snapshot.
+ * Readings (not fixed by the paper):
+ *   - U_t = 1 iff the sample-stream map of SplitMix64 started from
+ *     seed XOR ORACLE_SVRG_TAG gives index 0 for counter t (probability 1/n);
+ *   - an iteration with U_t = 1 computes the snapshot and makes no step;
+ *   - a snapshot is taken at x0 before the first iteration. */
+#define ORACLE_SVRG_TAG 0xA5A5A5A5A5A5A5A5ull
+
+int oracle_svrg_full_gradient_due(uint64_t seed, uint64_t t, int64_t n) {
+    return oracle_sample(seed ^ ORACLE_SVRG_TAG, t, n) == 0;
+}
+
+/* The snapshot at x: alpha_i = phi'(a_i . x; b_i), abar = (1/n) sum alpha_i a_i. */
+void oracle_svrg_snapshot(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                          const double* b, int loss, const double* x, double* alpha, double* abar) {
+    for (int64_t v = 0; v < d; ++v) abar[v] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double z = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) z += val[k] * x[colidx[k]];
+        alpha[i] = oracle_dphi(z, b[i], loss);
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) abar[colidx[k]] += alpha[i] * val[k];
+    }
+    for (int64_t v = 0; v < d; ++v) abar[v] /= (double)n;
+}
+
+/* One sparse SVRG inner step on sample i: x only; alpha and abar stay. */
+static void sparse_svrg_step(int64_t i, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                             const double* b, int loss, double lambda, const double* D, double gamma, double* x,
+                             const double* alpha, const double* abar) {
+    int64_t s = rowptr[i], e = rowptr[i + 1];
+    double z = 0.0;
+    for (int64_t k = s; k < e; ++k) z += val[k] * x[colidx[k]];
+    double delta = oracle_dphi(z, b[i], loss) - alpha[i];
+    for (int64_t k = s; k < e; ++k) {
+        int32_t v = colidx[k];
+        double xo = x[v];
+        x[v] = xo - gamma * (delta * val[k] + D[v] * (abar[v] + lambda * xo));
+    }
+}
+
+/* Inner steps on an explicit list of samples (no snapshot). */
+int oracle_svrg_indices(const int64_t* rowptr, const int32_t* colidx, const double* val, const double* b, int loss,
+                        double lambda, const double* D, double gamma, int64_t n, const int64_t* idx, int64_t count,
+                        double* x, const double* alpha, const double* abar) {
+    for (int64_t s = 0; s < count; ++s) {
+        if (idx[s] < 0 || idx[s] >= n) return -1;
+        sparse_svrg_step(idx[s], rowptr, colidx, val, b, loss, lambda, D, gamma, x, alpha, abar);
+    }
+    return 0;
+}
+
+/* Iterations t = t0 .. t0+count-1: snapshot where U_t = 1, otherwise an
+ * inner step on sample i_t of the seeded stream. */
+int oracle_svrg_run(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                    const double* b, int loss, double lambda, const double* D, double gamma, uint64_t seed,
+                    uint64_t t0, int64_t count, double* x, double* alpha, double* abar) {
+    for (int64_t s = 0; s < count; ++s) {
+        uint64_t t = t0 + (uint64_t)s;
+        if (oracle_svrg_full_gradient_due(seed, t, n))
+            oracle_svrg_snapshot(n, d, rowptr, colidx, val, b, loss, x, alpha, abar);
+        else
+            sparse_svrg_step(oracle_sample(seed, t, n), rowptr, colidx, val, b, loss, lambda, D, gamma, x, alpha,
+                             abar);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* objective and gradient, Neumaier-compensated sums                   */
 /* ------------------------------------------------------------------ */
 

@@ -109,3 +109,64 @@ def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     with np.errstate(all="ignore"):
         assert not pins_pass(build_mutant(tmp_path, name, old, new)), name
+
+
+# Planted mistakes in the sparse SVRG path, against its own pins.
+SVRG_MUTANTS = {
+    "svrg snapshot sign": ("alpha[i] = oracle_dphi(z, b[i], loss);", "alpha[i] = -oracle_dphi(z, b[i], loss);"),
+    "svrg snapshot average not divided": ("abar[v] /= (double)n;", "abar[v] /= 1.0;"),
+    "svrg step drops lambda": ("D[v] * (abar[v] + lambda * xo)", "D[v] * (abar[v])"),
+    "svrg step drops the snapshot gradient": ("D[v] * (abar[v] + lambda * xo)", "D[v] * (lambda * xo)"),
+    "svrg full gradient never due": ("return oracle_sample(seed ^ ORACLE_SVRG_TAG, t, n) == 0;", "return 0;"),
+    "svrg full gradient always due": ("return oracle_sample(seed ^ ORACLE_SVRG_TAG, t, n) == 0;", "return 1;"),
+}
+
+
+def svrg_pins_pass(lib) -> bool:
+    """A compact run of the SVRG pins; False as soon as one fails."""
+    try:
+        rng = np.random.default_rng(7)
+        n, T = 500, 200_000
+        due = sum(lib.oracle_svrg_full_gradient_due(3, t, n) for t in range(T))
+        if abs(due - T / n) > 5 * np.sqrt(T / n):
+            return False
+        p = random_sparse(rng, 30, 10, 0.35, oracle.LOGISTIC, 0.05)
+        sv = oracle.SparseSvrg(p, lib=lib)
+        A = p.dense()
+        xt = rng.standard_normal(p.d) * 0.5
+        snap = oracle.State(xt.copy(), np.zeros(p.n), np.zeros(p.d))
+        sv.snapshot(snap)
+        zt = A @ xt
+        alpha = -p.b * np.exp(-np.logaddexp(0.0, p.b * zt))
+        if not (rel_err(snap.alpha, alpha) < 1e-13 and rel_err(snap.abar, A.T @ alpha / p.n) < 1e-13):
+            return False
+        x = rng.standard_normal(p.d) * 0.5
+        dirs = []
+        for i in range(p.n):
+            s = oracle.State(x.copy(), snap.alpha.copy(), snap.abar.copy())
+            sv.run_indices([i], s)
+            dirs.append((x - s.x) / sv.gamma)
+        z = A @ x
+        grad = A.T @ (-p.b * np.exp(-np.logaddexp(0.0, p.b * z))) / p.n + p.lam * x
+        if not rel_err(np.mean(dirs, axis=0), grad) < 1e-13:
+            return False
+        q = random_sparse(rng, 60, 10, 0.35, oracle.SQUARED, 0.2)
+        sq = oracle.SparseSvrg(q, seed=4, lib=lib)
+        sq.epochs(400)
+        Aq = q.dense()
+        xstar = np.linalg.solve(Aq.T @ Aq / q.n + 0.2 * np.eye(q.d), Aq.T @ q.b / q.n)
+        return bool(rel_err(sq.state.x, xstar) < 1e-10)
+    except (RuntimeError, FloatingPointError, np.linalg.LinAlgError):
+        return False
+
+
+def test_unmutated_oracle_passes_svrg_pins(tmp_path):
+    lib = build_mutant(tmp_path, "identity", "#include <math.h>", "#include <math.h>")
+    assert svrg_pins_pass(lib)
+
+
+@pytest.mark.parametrize("name", sorted(SVRG_MUTANTS))
+def test_svrg_mutant_is_caught(tmp_path, name):
+    old, new = SVRG_MUTANTS[name]
+    with np.errstate(all="ignore"):
+        assert not svrg_pins_pass(build_mutant(tmp_path, name, old, new)), name

@@ -346,3 +346,100 @@ def test_step_size_rule():
     q.lam = 0.5
     sq = oracle.SparseSaga(q)
     assert sq.gamma == pytest.approx(1 / (0.5 * sq.D.max()), rel=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# sparse SVRG with randomly timed full gradients (Appendix C)
+# ---------------------------------------------------------------------------
+
+def dense_dphi(z, b, loss):
+    if loss == oracle.SQUARED:
+        return z - b
+    return -b * np.exp(-np.logaddexp(0.0, b * z))        # -b / (1 + exp(b z)), stably
+
+
+def test_svrg_full_gradient_rate_is_one_over_n():
+    sv_lib = oracle.load()
+    n, T = 1000, 400_000
+    due = np.array([sv_lib.oracle_svrg_full_gradient_due(7, t, n) for t in range(T)])
+    expected = T / n
+    assert abs(due.sum() - expected) < 5 * np.sqrt(expected)
+    # a stream of its own: not the sample stream's index 0
+    idx = oracle.sample_stream(7, 0, T, n)
+    assert abs(np.sum(due & (idx == 0)) - T / n ** 2) < 5 * np.sqrt(T / n ** 2) + 1
+
+
+@pytest.mark.parametrize("loss", [oracle.LOGISTIC, oracle.SQUARED])
+def test_svrg_snapshot_is_dense_phi_prime_and_its_average(loss):
+    rng = np.random.default_rng(11)
+    p = random_sparse(rng, 40, 15, 0.3, loss, 0.05)
+    sv = oracle.SparseSvrg(p)
+    A = p.dense()
+    x = rng.standard_normal(p.d)
+    s = oracle.State(x.copy(), np.zeros(p.n), np.zeros(p.d))
+    sv.snapshot(s)
+    alpha = dense_dphi(A @ x, p.b, loss)
+    assert rel_err(s.alpha, alpha) < 1e-13
+    assert rel_err(s.abar, A.T @ alpha / p.n) < 1e-13
+    assert np.array_equal(s.x, x)
+
+
+def test_svrg_inner_steps_leave_the_memory_alone():
+    rng = np.random.default_rng(12)
+    p = random_sparse(rng, 30, 12, 0.3, oracle.LOGISTIC, 0.05)
+    sv = oracle.SparseSvrg(p)
+    sv.run_indices(rng.integers(0, p.n, size=50))
+    s0 = sv.state.copy()
+    sv.run_indices(rng.integers(0, p.n, size=50))
+    assert np.array_equal(sv.state.alpha, s0.alpha) and np.array_equal(sv.state.abar, s0.abar)
+    assert not np.array_equal(sv.state.x, s0.x)
+
+
+@pytest.mark.parametrize("loss", [oracle.LOGISTIC, oracle.SQUARED])
+def test_svrg_expected_step_is_the_gradient(loss):
+    # memory from a snapshot at x~, iterate at another x: averaged over all i,
+    # the sparse SVRG direction is grad f(x) (Appendix B's unbiasedness, the
+    # D_i reweighting of the snapshot's full gradient and of the L2 term)
+    rng = np.random.default_rng(13)
+    p = random_sparse(rng, 25, 9, 0.35, loss, 0.07)
+    sv = oracle.SparseSvrg(p)
+    A = p.dense()
+    xt = rng.standard_normal(p.d) * 0.5
+    snap = oracle.State(xt.copy(), np.zeros(p.n), np.zeros(p.d))
+    sv.snapshot(snap)
+    x = rng.standard_normal(p.d) * 0.5
+    dirs = []
+    for i in range(p.n):
+        s = oracle.State(x.copy(), snap.alpha.copy(), snap.abar.copy())
+        sv.run_indices([i], s)
+        dirs.append((x - s.x) / sv.gamma)
+    grad = A.T @ dense_dphi(A @ x, p.b, loss) / p.n + p.lam * x
+    assert rel_err(np.mean(dirs, axis=0), grad) < 1e-13
+
+
+def test_svrg_step_at_the_snapshot_is_the_reweighted_full_gradient():
+    rng = np.random.default_rng(14)
+    p = random_sparse(rng, 20, 8, 0.4, oracle.LOGISTIC, 0.03)
+    sv = oracle.SparseSvrg(p)
+    A = p.dense()
+    x = rng.standard_normal(p.d)
+    snap = oracle.State(x.copy(), np.zeros(p.n), np.zeros(p.d))
+    sv.snapshot(snap)
+    full = A.T @ dense_dphi(A @ x, p.b, oracle.LOGISTIC) / p.n + p.lam * x
+    cnt = (A != 0).sum(axis=0)
+    D = np.where(cnt > 0, p.n / np.maximum(cnt, 1), 0.0)
+    for i in (0, 7, 19):
+        s = oracle.State(x.copy(), snap.alpha.copy(), snap.abar.copy())
+        sv.run_indices([i], s)
+        on = (A[i] != 0).astype(float)
+        assert rel_err((x - s.x) / sv.gamma, on * D * full) < 1e-13
+
+
+def test_svrg_converges_to_the_ridge_closed_form():
+    rng = np.random.default_rng(15)
+    p = random_sparse(rng, 60, 10, 0.35, oracle.SQUARED, 0.2)
+    sv = oracle.SparseSvrg(p, seed=4)
+    sv.epochs(400)
+    A = p.dense()
+    xstar = np.linalg.solve(A.T @ A / p.n + 0.2 * np.eye(p.d), A.T @ p.b / p.n)
+    assert rel_err(sv.state.x, xstar) < 1e-10
