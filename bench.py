@@ -386,10 +386,13 @@ def main():
                 "final_rel_subopt": rel, "waves": ti.waves, "threads_per_block": ti.threads_per_block,
                 "hot_columns": ti.hot_columns, "gamma": ti.gamma, "gamma_over_serial_rule": ti.gamma * 3.0 * ti.L}
 
-    tta = tta_tuned = None
+    tta = tta_tuned = tta_svrg = None
     if not args.skip_tta:
         tta = time_to_target(step, shape)
         log(f"time to 1e-9 (benchmarked shape): {tta}")
+        # sparse SVRG (Appendix C variant) on the same kernel, shape and step
+        tta_svrg = time_to_target(step, dict(shape, method=A.ASAGA_METHOD_SVRG))
+        log(f"time to 1e-9 (sparse SVRG, same shape and step): {tta_svrg}")
         if tune is not None:
             tta_tuned = time_to_target(tta_step, tta_shape)
             log(f"time to 1e-9 (autotuned shape): {tta_tuned}")
@@ -437,6 +440,7 @@ def main():
                      "launch_ms": avg_launch_s * 1e3},
         "time_to_1e-9": tta,
         "time_to_1e-9_autotuned": tta_tuned,
+        "time_to_1e-9_svrg": tta_svrg,
         "autotune": tune,
         "batched": batched,
         "tau_sweep": sweep,

@@ -98,6 +98,17 @@ extern "C" {
 #define ASAGA_PREC_MIXED 1 /* x, alpha in FP32 (phi' rounded to FP32 before delta
                               is formed); abar and D in FP64                       */
 
+/* method (single-instance contexts) */
+#define ASAGA_METHOD_SAGA 0 /* Sparse SAGA (Eq. SparseSAGA), the memory updated by every step */
+#define ASAGA_METHOD_SVRG 1 /* sparse SVRG with randomly timed full gradients (Appendix C):
+                               at iteration t, with probability 1/n (U_t = 1 iff
+                               floor(n * SplitMix64(seed XOR 0xA5A5A5A5A5A5A5A5, t) / 2^64)
+                               == 0) the memory is reset to the snapshot of the current x,
+                               alpha_i = phi'(a_i . x), abar = (1/n) sum alpha_i a_i, and no
+                               step is made; otherwise sample i_t takes the Sparse SAGA step
+                               with the memory held fixed.  A snapshot is also taken at x0.
+                               Snapshots are synchronised (between launches)           */
+
 typedef struct asaga_ctx asaga_ctx;
 
 /* The data of the problem.  CSR requirements (checked by asaga_init):
@@ -168,7 +179,8 @@ typedef struct asaga_opts {
     int32_t plain_launch;     /* batched: 1 launches each epoch's kernel directly;
                                  0 (default) replays the epochs of one
                                  asaga_epochs call as a captured hipGraph        */
-    int32_t reserved;         /* must be 0                                         */
+    int32_t method;           /* ASAGA_METHOD_* (SVRG: single-instance contexts,
+                                 not racy)                                        */
     void* stream;             /* hipStream_t */
 } asaga_opts;
 

@@ -54,6 +54,8 @@ ASAGA_MODE_SERIAL = 0
 ASAGA_MODE_ASYNC = 1
 ASAGA_PREC_F64 = 0
 ASAGA_PREC_MIXED = 1
+ASAGA_METHOD_SAGA = 0
+ASAGA_METHOD_SVRG = 1
 
 ERROR_NAMES = {0: "ASAGA_OK", -1: "ASAGA_E_ARG", -2: "ASAGA_E_CSR", -3: "ASAGA_E_OOM", -4: "ASAGA_E_HIP",
                -5: "ASAGA_E_DIVERGED", -6: "ASAGA_E_STATE"}
@@ -71,7 +73,7 @@ class asaga_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("waves", ctypes.c_int32), ("lanes_per_sample", ctypes.c_int32),
                 ("racy", ctypes.c_int32), ("hot_columns", ctypes.c_int32), ("flush_every", ctypes.c_int32),
                 ("threads_per_block", ctypes.c_int32), ("hot_tier_columns", ctypes.c_int32),
-                ("hot_tier_every", ctypes.c_int32), ("plain_launch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("hot_tier_every", ctypes.c_int32), ("plain_launch", ctypes.c_int32), ("method", ctypes.c_int32),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -302,7 +304,8 @@ class Solver:
     def __init__(self, n, d, rowptr, colidx, val, b, lam, loss=ASAGA_LOSS_LOGISTIC, val_dtype=None,
                  mode=ASAGA_MODE_SERIAL, precision=ASAGA_PREC_F64, step=0.0, seed=0, waves=0,
                  lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, threads_per_block=0,
-                 hot_tier_columns=0, hot_tier_every=0, plain_launch=0, stream=None, batch=None):
+                 hot_tier_columns=0, hot_tier_every=0, plain_launch=0, method=ASAGA_METHOD_SAGA, stream=None,
+                 batch=None):
         self.n, self.d = int(n), int(d)
         arrays = (rowptr, colidx, val, b)
         on_dev = [_is_torch_cuda(a) for a in arrays]
@@ -331,7 +334,7 @@ class Solver:
             stream = stream.cuda_stream
         self.opts = asaga_opts(float(step), int(seed), int(mode), int(precision), int(waves), int(lanes_per_sample),
                                int(racy), int(hot_columns), int(flush_every), int(threads_per_block),
-                               int(hot_tier_columns), int(hot_tier_every), int(plain_launch), 0, stream)
+                               int(hot_tier_columns), int(hot_tier_every), int(plain_launch), int(method), stream)
         if batch is None:
             self.ctx = asaga_init(self.prob, self.opts)
             self.n_inst = 1

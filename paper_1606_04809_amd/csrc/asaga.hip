@@ -70,6 +70,7 @@ struct asaga_ctx {
     asaga_opts o{};
     hipStream_t st = nullptr;
     bool mixed = false;
+    bool svrg = false;           // ASAGA_METHOD_SVRG
     UpdateShape shape{};
     std::vector<Inst> inst;
     InstArgs* d_insts = nullptr;
@@ -215,7 +216,9 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
         return fail(nullptr, ASAGA_E_ARG, "threads_per_block must be 0 or a multiple of 64 up to 1024");
     if (o->plain_launch != 0 && o->plain_launch != 1) return fail(nullptr, ASAGA_E_ARG, "plain_launch must be 0 or 1");
-    if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
+    if (o->method != ASAGA_METHOD_SAGA && o->method != ASAGA_METHOD_SVRG)
+        return fail(nullptr, ASAGA_E_ARG, "bad method");
+    if (o->method == ASAGA_METHOD_SVRG && o->racy) return fail(nullptr, ASAGA_E_ARG, "racy applies to SAGA only");
     return ASAGA_OK;
 }
 
@@ -246,7 +249,7 @@ InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
     a.t0 = t0;
     a.count = count;
     a.blocks = 0;
-    a.reserved = 0;
+    a.frozen = 0;
     a.tau_log = nullptr;
     a.tau_count = nullptr;
     a.tau_cap = 0;
@@ -257,11 +260,48 @@ InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
 XView x_view(const asaga_ctx* c, const Inst& I) { return c->mixed ? XView{I.xa, 4, 1} : XView{I.xa, 2, 0}; }
 XView abar_view(const Inst& I) { return XView{I.xa + 1, 2, 0}; }
 
+// ---- sparse SVRG (Appendix C): randomly timed, synchronised snapshots ----
+
+// host copy of the sample-stream map (SplitMix64 of Steele, Lea & Flood
+// 2014, Lemire's multiply-high to [0, n)), for the full-gradient decisions
+uint64_t host_splitmix64(uint64_t seed, uint64_t t) {
+    uint64_t z = seed + (t + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr uint64_t kSvrgTag = 0xA5A5A5A5A5A5A5A5ull;
+
+// U_t: whether iteration t of an SVRG run takes a full gradient
+bool svrg_full_gradient_due(uint64_t seed, uint64_t t, int64_t m) {
+    return (uint64_t)(((unsigned __int128)host_splitmix64(seed ^ kSvrgTag, t) * (uint64_t)m) >> 64) == 0;
+}
+
+// The snapshot at the current x: alpha_j = phi'(a_j . x), abar = (1/m) sum alpha_j a_j.
+int svrg_snapshot(asaga_ctx* c, Inst& I) {
+    const MatArgs A = mat(c);
+    HIPCHK(c, launch_rowdot(A, I.rows, I.m, x_view(c, I), c->z, c->st));
+    if (c->mixed) {
+        HIPCHK(c, launch_dphi_coef(A, I.rows, I.m, c->z, 1.0, c->tmp, c->st));
+        HIPCHK(c, launch_narrow_f64(c->tmp, I.m, static_cast<float*>(I.alpha), c->st));
+    } else {
+        HIPCHK(c, launch_dphi_coef(A, I.rows, I.m, c->z, 1.0, static_cast<double*>(I.alpha), c->st));
+    }
+    // abar from the stored memory (so that it is the exact average of what steps read)
+    HIPCHK(c, launch_alpha_coef(I.alpha, c->mixed, I.m, 1.0 / (double)I.m, c->tmp, c->st));
+    HIPCHK(c, launch_fill_f64(I.xa + 1, 0.0, c->d, 2, c->st));
+    HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.xa + 1, 2, c->st));
+    return ASAGA_OK;
+}
+
 int zero_state(asaga_ctx* c, Inst& I) {
     HIPCHK(c, launch_fill_f64(I.xa, 0.0, 2 * c->d, 1, c->st));
     if (c->mixed) HIPCHK(c, launch_fill_f32(static_cast<float*>(I.alpha), 0.0f, I.m, c->st));
     else HIPCHK(c, launch_fill_f64(static_cast<double*>(I.alpha), 0.0, I.m, 1, c->st));
     I.t = 0;
+    // SVRG starts from a snapshot at x0 = 0
+    if (c->svrg) return svrg_snapshot(c, I);
     return ASAGA_OK;
 }
 
@@ -494,6 +534,7 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
             return fail(nullptr, ASAGA_E_ARG, "bad batch descriptor");
         if (o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "batched solves run in async mode");
         if (o->racy) return fail(nullptr, ASAGA_E_ARG, "racy is not available for batched solves");
+        if (o->method != ASAGA_METHOD_SAGA) return fail(nullptr, ASAGA_E_ARG, "batched solves run Sparse SAGA");
         for (int k = 0; k < bt->n_inst; ++k) {
             if (!(bt->inst_lambda[k] > 0.0) || !std::isfinite(bt->inst_lambda[k]))
                 return fail(nullptr, ASAGA_E_ARG, "instance lambda must be > 0 and finite");
@@ -515,6 +556,7 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
     c->loss = p->loss;
     c->val_dtype = p->val_dtype;
     c->mixed = o->precision == ASAGA_PREC_MIXED;
+    c->svrg = o->method == ASAGA_METHOD_SVRG;
 
     auto bail = [&](int code) {
         std::string msg = c->err;
@@ -864,8 +906,22 @@ int asaga_updates(asaga_ctx* c, int64_t count) {
     // serial launches are cut into pieces of at most 2^18 updates
     const int64_t piece = S.serial ? ((int64_t)1 << 18) : count;
     for (int64_t done = 0; done < count;) {
-        const int64_t k = count - done < piece ? count - done : piece;
+        int64_t k = count - done < piece ? count - done : piece;
+        if (c->svrg) {
+            // a full gradient at iteration I.t, else inner steps up to the next one
+            if (svrg_full_gradient_due(I.seed, (uint64_t)I.t, I.m)) {
+                int rc = svrg_snapshot(c, I);
+                if (rc) return rc;
+                I.t += 1;
+                done += 1;
+                continue;
+            }
+            int64_t run = 1;
+            while (run < k && !svrg_full_gradient_due(I.seed, (uint64_t)(I.t + run), I.m)) ++run;
+            k = run;
+        }
         InstArgs a = inst_args(I, (uint64_t)I.t, (uint64_t)k);
+        a.frozen = c->svrg ? 1 : 0;
         if (c->tau_on) {
             a.tau_log = c->d_tau;
             a.tau_count = c->d_tau_count;

@@ -29,7 +29,8 @@ struct InstArgs {
     uint64_t t0;          // sample counter of the first update of this launch
     uint64_t count;       // updates this launch applies to the instance (0: skip it)
     int32_t blocks;       // batched: workgroups serving the instance
-    int32_t reserved;
+    int32_t frozen;       // 1: the memory (alpha, abar) is held fixed, only x is written
+                          //    (the inner steps of sparse SVRG)
     // overlap log (nullptr: off): a sample whose counter hashes to 0 modulo
     // kTauEvery (an independent thinning, unrelated to which lane group or
     // round runs it) takes the next entry e = (*tau_count)++ below tau_cap and

@@ -268,11 +268,13 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
     // write phase: x_c += -gamma (delta a_c + D_c (abar_c + lambda x_hat_c)) on even lanes,
     //              abar_c += delta a_c / m on odd lanes
     const double gam = I.gamma, lam = I.lambda, dm = delta * I.inv_m;
+    // frozen memory: the odd lanes (abar) write nothing
+    const bool writes = !(I.frozen && comp == 1);
     if (len <= CAP) {
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             const int64_t q = (int64_t)p * E + e;
-            if (q < len) {
+            if (q < len && writes) {
                 const double w = comp == 0 ? -gam * (delta * vv[p] + dd[p] * (as[p] + lam * xs[p])) : dm * vv[p];
                 add_slot<RACY, MIXED>(I.xa, cc[p], comp, hot, w);
             }
@@ -287,10 +289,10 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
                 pr.a = lds[2 * c + 1] + lds[2 * hot + 2 * c + 1];
             }
             const double w = comp == 0 ? -gam * (delta * v + I.D[c] * (pr.a + lam * pr.x)) : dm * v;
-            add_slot<RACY, MIXED>(I.xa, c, comp, hot, w);
+            if (writes) add_slot<RACY, MIXED>(I.xa, c, comp, hot, w);
         }
     }
-    if (gl == 0) add_alpha<RACY, MIXED>(I.alpha, rr.j, delta);
+    if (gl == 0 && !I.frozen) add_alpha<RACY, MIXED>(I.alpha, rr.j, delta);
     if constexpr (SERIAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 

@@ -63,7 +63,7 @@ def expect(code, **changes):
     opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
                                                               "waves", "step", "loss", "hot_columns",
                                                               "flush_every", "threads_per_block",
-                                                              "plain_launch")}
+                                                              "plain_launch", "method")}
     kw.update(changes)
     with pytest.raises(A.AsagaError) as ei:
         A.Solver(**kw, **opts)
@@ -105,6 +105,8 @@ def test_bad_arguments_are_rejected():
     expect(E, threads_per_block=2048)
     expect(E, threads_per_block=1088)
     expect(E, plain_launch=2)
+    expect(E, method=2)
+    expect(E, method=A.ASAGA_METHOD_SVRG, racy=1, mode=A.ASAGA_MODE_ASYNC)   # racy is a SAGA control
     expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
 
 
@@ -163,3 +165,11 @@ def test_overlap_estimator_rejects_bad_input():
         A.asaga_overlap_estimate(np.array([[1, 5]]), every=1, clock_hz=0.0)
     r = A.asaga_overlap_estimate(np.zeros((4, 2), dtype=np.int64), every=1, clock_hz=1.0)
     assert r.logged == 0
+
+
+def test_batched_svrg_is_rejected():
+    kw = good()
+    with pytest.raises(A.AsagaError) as ei:
+        A.Solver(**kw, mode=A.ASAGA_MODE_ASYNC, method=A.ASAGA_METHOD_SVRG,
+                 batch=(np.zeros(3, np.int8), np.array([-1], np.int32), np.array([0.1])))
+    assert ei.value.code == A.ASAGA_E_ARG

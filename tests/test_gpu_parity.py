@@ -428,6 +428,59 @@ def test_mixed_precision_reaches_1e9():
         assert err < 1e-6
 
 
+def compare_svrg_serial(p, epochs, seed=0, tol=1e-12):
+    sv = oracle.SparseSvrg(p, seed=seed)
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, method=A.ASAGA_METHOD_SVRG, seed=seed) as g:
+        x, alpha, abar, t = g.get_state()
+        assert rel_err(alpha, sv.state.alpha) <= tol and rel_err(abar, sv.state.abar) <= tol   # snapshot at x0
+        for e in range(epochs):
+            g.epochs(1)
+            sv.epochs(1)
+            x, alpha, abar, t = g.get_state()
+            assert t == sv.state.t
+            errs = (rel_err(x, sv.state.x), rel_err(alpha, sv.state.alpha), rel_err(abar, sv.state.abar))
+            assert max(errs) <= tol, (e, errs)
+    return sum(sv.full_gradient_due(t) for t in range(sv.state.t))
+
+
+def test_svrg_serial_parity_config1():
+    """Sparse SVRG with randomly timed full gradients, one wavefront in
+    stream order: iterates, snapshot memory and its average match the
+    oracle after every epoch (about one snapshot per epoch)."""
+    p = datagen.config1(n=400, d=120, k=12)
+    snaps = compare_svrg_serial(p, 12, seed=3)
+    say(f"svrg serial: {snaps} full gradients in 12 epochs")
+    assert snaps >= 3
+
+
+@pytest.mark.parametrize("loss", [datagen.LOGISTIC, datagen.SQUARED])
+def test_svrg_serial_parity_ragged(loss):
+    p = ragged_problem(seed=5, loss=loss, lam=0.01)
+    compare_svrg_serial(p, 6, seed=1)
+
+
+def test_svrg_async_reaches_optimum():
+    p = datagen.config2(n=20_000, d=5000)
+    r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, method=A.ASAGA_METHOD_SVRG, waves=64) as g:
+        ep, rel = run_to(g, r["f_lower"], target=1e-10, max_epochs=300, every=5)
+        say(f"svrg async (64 waves): {ep} epochs, rel {rel:.2e}")
+        assert rel <= 1e-10
+        # the memory is the snapshot's: abar is still the exact average of alpha
+        x, alpha, abar, t = g.get_state()
+        assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-12
+
+
+@pytest.mark.slow
+def test_svrg_async_config2_full_reaches_1e9(golden):
+    p = datagen.config2()
+    fstar = golden["config2"]["f_lower"]
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, method=A.ASAGA_METHOD_SVRG) as g:
+        ep, rel = run_to(g, fstar, max_epochs=200, every=1)
+        say(f"svrg async config2: {ep} epochs, rel {rel:.2e}")
+        assert rel <= 1e-9
+
+
 def test_overlap_log_counts_samples_in_flight():
     """The sampled overlap log of asaga_overlap: the updates in flight at a
     read grow with the wavefronts in flight, match Little's law
