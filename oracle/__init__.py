@@ -54,6 +54,8 @@ _SIGS = {
     "oracle_objective": (_D, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P]),
     "oracle_gradient": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P, _P]),
     "oracle_memory_average": (_I, [_I64, _I64, _P, _P, _P, _P, _P]),
+    "oracle_dense_saga_run": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _D, _U64, _U64, _I64, _P, _P, _P]),
+    "oracle_lagged_saga_run": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _D, _U64, _U64, _I64, _P, _P, _P, _P]),
     "oracle_svrg_full_gradient_due": (_I, [_U64, _U64, _I64]),
     "oracle_svrg_snapshot": (None, [_I64, _I64, _P, _P, _P, _P, _I, _P, _P, _P]),
     "oracle_svrg_indices": (_I, [_P, _P, _P, _P, _I, _D, _P, _D, _I64, _P, _I64, _P, _P, _P]),
@@ -216,6 +218,43 @@ class SparseSaga:
         f = self.objective(x)
         g = self.gradient(x)
         return f, f - float(g @ g) / (2.0 * self.lam)
+
+
+class DenseSaga(SparseSaga):
+    """Serial FP64 dense SAGA (every coordinate receives abar + lambda x at
+    every step), the baseline of the Appendix F comparison.  Same sample
+    stream and step rule as Sparse SAGA."""
+
+    def run(self, updates: int, state: State | None = None) -> State:
+        s = self.state if state is None else state
+        rc = self.lib.oracle_dense_saga_run(self.n, self.d, _p(self.rowptr), _p(self.colidx), _p(self.val), _p(self.b),
+                                            self.loss, self.lam, self.gamma, self.seed, s.t, int(updates), _p(s.x),
+                                            _p(s.alpha), _p(s.abar))
+        if rc != 0:
+            raise RuntimeError(f"oracle_dense_saga_run failed ({rc})")
+        s.t += int(updates)
+        return s
+
+
+class LaggedSaga(SparseSaga):
+    """Serial FP64 lagged-update SAGA (Appendix F): dense SAGA's iterates with
+    the dense part of each step deferred to the next read of a coordinate."""
+
+    def __init__(self, prob, step: float | None = None, seed: int = 0, lib=None):
+        super().__init__(prob, step=step, seed=seed, lib=lib)
+        self.last = np.zeros(self.d, dtype=np.uint64)
+
+    def run(self, updates: int, state: State | None = None) -> State:
+        s = self.state if state is None else state
+        if s.t != 0 and not np.all(self.last == s.t):
+            raise RuntimeError("lagged counters out of step with the state")
+        rc = self.lib.oracle_lagged_saga_run(self.n, self.d, _p(self.rowptr), _p(self.colidx), _p(self.val),
+                                             _p(self.b), self.loss, self.lam, self.gamma, self.seed, s.t, int(updates),
+                                             _p(s.x), _p(s.alpha), _p(s.abar), _p(self.last))
+        if rc != 0:
+            raise RuntimeError(f"oracle_lagged_saga_run failed ({rc})")
+        s.t += int(updates)
+        return s
 
 
 class SparseSvrg(SparseSaga):

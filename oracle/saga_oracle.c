@@ -250,6 +250,79 @@ int oracle_svrg_run(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* 
 }
 
 /* ------------------------------------------------------------------ */
+/* dense and lagged SAGA (Appendix F), for the comparison with Sparse  */
+/* SAGA; serial only                                                   */
+/* ------------------------------------------------------------------ */
+
+/* Dense SAGA with the linear-model memory (Eq. SAGAupdate of Section 2):
+ *     x+ = x - gamma ((phi'(a_i . x) - alpha_i) a_i + abar + lambda x)
+ * over every coordinate, then abar += (delta/n) a_i, alpha_i += delta. */
+int oracle_dense_saga_run(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                          const double* b, int loss, double lambda, double gamma, uint64_t seed, uint64_t t0,
+                          int64_t count, double* x, double* alpha, double* abar) {
+    for (int64_t s = 0; s < count; ++s) {
+        int64_t i = oracle_sample(seed, t0 + (uint64_t)s, n);
+        double z = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) z += val[k] * x[colidx[k]];
+        double delta = oracle_dphi(z, b[i], loss) - alpha[i];
+        /* the memory average and the L2 term reach every coordinate (read before the write) */
+        for (int64_t v = 0; v < d; ++v) x[v] = x[v] - gamma * (abar[v] + lambda * x[v]);
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            x[colidx[k]] -= gamma * delta * val[k];
+            abar[colidx[k]] += delta * val[k] / (double)n;
+        }
+        alpha[i] += delta;
+    }
+    return 0;
+}
+
+/* Bring coordinate v from iteration last[v] to iteration t: each skipped
+ * dense step was x_v <- (1 - gamma lambda) x_v - gamma abar_v with abar_v
+ * unchanged (it changes only when v is in a sampled support), so after k
+ * steps x_v = q (x_v + abar_v / lambda) - abar_v / lambda, q = (1 - gamma lambda)^k. */
+static void lagged_catch_up(int64_t v, uint64_t t, double gamma, double lambda, double* x, const double* abar,
+                            uint64_t* last) {
+    uint64_t k = t - last[v];
+    if (k == 0) return;
+    double lq = (double)k * log1p(-gamma * lambda);
+    double q = exp(lq);
+    /* q x - (1 - q) abar / lambda, with 1 - q = -expm1(lq) free of cancellation */
+    x[v] = q * x[v] + expm1(lq) * abar[v] / lambda;
+    last[v] = t;
+}
+
+/* Lagged SAGA (the lagged-update implementation Appendix F compares with):
+ * the dense part of each step is applied to a coordinate only when a
+ * sampled support next reads it (last[v] holds the iteration x_v is current
+ * at); the same iterates as dense SAGA, computed on the supports only.
+ * All coordinates are brought up to date at the end of the call. */
+int oracle_lagged_saga_run(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                           const double* b, int loss, double lambda, double gamma, uint64_t seed, uint64_t t0,
+                           int64_t count, double* x, double* alpha, double* abar, uint64_t* last) {
+    if (!(lambda > 0.0)) return -1;
+    for (int64_t s = 0; s < count; ++s) {
+        uint64_t t = t0 + (uint64_t)s;
+        int64_t i = oracle_sample(seed, t, n);
+        double z = 0.0;
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            lagged_catch_up(colidx[k], t, gamma, lambda, x, abar, last);
+            z += val[k] * x[colidx[k]];
+        }
+        double delta = oracle_dphi(z, b[i], loss) - alpha[i];
+        for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            int32_t v = colidx[k];
+            double xo = x[v];
+            x[v] = xo - gamma * (delta * val[k] + abar[v] + lambda * xo);
+            abar[v] += delta * val[k] / (double)n;
+            last[v] = t + 1;
+        }
+        alpha[i] += delta;
+    }
+    for (int64_t v = 0; v < d; ++v) lagged_catch_up(v, t0 + (uint64_t)count, gamma, lambda, x, abar, last);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* objective and gradient, Neumaier-compensated sums                   */
 /* ------------------------------------------------------------------ */
 

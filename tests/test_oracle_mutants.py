@@ -170,3 +170,50 @@ def test_svrg_mutant_is_caught(tmp_path, name):
     old, new = SVRG_MUTANTS[name]
     with np.errstate(all="ignore"):
         assert not svrg_pins_pass(build_mutant(tmp_path, name, old, new)), name
+
+
+# Planted mistakes in the dense and lagged SAGA paths.
+DENSE_LAGGED_MUTANTS = {
+    "dense drops lambda": ("x[v] = x[v] - gamma * (abar[v] + lambda * x[v]);", "x[v] = x[v] - gamma * (abar[v]);"),
+    "dense drops abar": ("x[v] = x[v] - gamma * (abar[v] + lambda * x[v]);", "x[v] = x[v] - gamma * (lambda * x[v]);"),
+    "lagged catch-up sign": ("x[v] = q * x[v] + expm1(lq) * abar[v] / lambda;",
+                             "x[v] = q * x[v] - expm1(lq) * abar[v] / lambda;"),
+    "lagged forgets the decay": ("x[v] = q * x[v] + expm1(lq) * abar[v] / lambda;",
+                                 "x[v] = x[v] + expm1(lq) * abar[v] / lambda;"),
+    "lagged counter not advanced": ("            last[v] = t + 1;\n", "            last[v] = t;\n"),
+}
+
+
+def dense_lagged_pins_pass(lib) -> bool:
+    try:
+        rng = np.random.default_rng(9)
+        p = random_sparse(rng, 60, 10, 0.35, oracle.SQUARED, 0.2)
+        sv = oracle.DenseSaga(p, seed=2, lib=lib)
+        sv.epochs(600)
+        A = p.dense()
+        xstar = np.linalg.solve(A.T @ A / p.n + 0.2 * np.eye(p.d), A.T @ p.b / p.n)
+        if not rel_err(sv.state.x, xstar) < 1e-10:
+            return False
+        q = random_sparse(rng, 80, 30, 0.1, oracle.LOGISTIC, 0.01)
+        dense = oracle.DenseSaga(q, seed=5, lib=lib)
+        lag = oracle.LaggedSaga(q, seed=5, lib=lib)
+        for _ in range(3):
+            dense.epochs(1)
+            lag.epochs(1)
+            if not rel_err(lag.state.x, dense.state.x) < 1e-12:
+                return False
+        return True
+    except (RuntimeError, FloatingPointError, np.linalg.LinAlgError):
+        return False
+
+
+def test_unmutated_oracle_passes_dense_lagged_pins(tmp_path):
+    lib = build_mutant(tmp_path, "identity", "#include <math.h>", "#include <math.h>")
+    assert dense_lagged_pins_pass(lib)
+
+
+@pytest.mark.parametrize("name", sorted(DENSE_LAGGED_MUTANTS))
+def test_dense_lagged_mutant_is_caught(tmp_path, name):
+    old, new = DENSE_LAGGED_MUTANTS[name]
+    with np.errstate(all="ignore"):
+        assert not dense_lagged_pins_pass(build_mutant(tmp_path, name, old, new)), name

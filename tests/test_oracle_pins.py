@@ -443,3 +443,47 @@ def test_svrg_converges_to_the_ridge_closed_form():
     A = p.dense()
     xstar = np.linalg.solve(A.T @ A / p.n + 0.2 * np.eye(p.d), A.T @ p.b / p.n)
     assert rel_err(sv.state.x, xstar) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# dense and lagged SAGA (Appendix F comparison)
+# ---------------------------------------------------------------------------
+
+def test_dense_saga_converges_to_the_ridge_closed_form():
+    rng = np.random.default_rng(21)
+    p = random_sparse(rng, 60, 10, 0.35, oracle.SQUARED, 0.2)
+    sv = oracle.DenseSaga(p, seed=2)
+    sv.epochs(600)
+    A = p.dense()
+    xstar = np.linalg.solve(A.T @ A / p.n + 0.2 * np.eye(p.d), A.T @ p.b / p.n)
+    assert rel_err(sv.state.x, xstar) < 1e-10
+
+
+def test_dense_saga_single_sample_is_gradient_descent():
+    a = np.array([0.4, 0.0, -1.2, 0.7])
+    one = csr_problem(a[None, :], [-1.0], 0.3, oracle.LOGISTIC)
+    sv = oracle.DenseSaga(one, step=0.4)
+    x = np.zeros(4)
+    sv.epochs(1)        # the first step's memory is zero: x1 = x0 - gamma (phi' a + lambda x0)
+    x = x - 0.4 * ((1.0 / (1 + np.exp(-(a @ x)))) * a + 0.3 * x)
+    assert rel_err(sv.state.x, x) < 1e-15
+    for _ in range(8):  # then the memory equals phi'(a . x_prev): the step is f'(x) exactly
+        sv.epochs(1)
+        x = x - 0.4 * ((1.0 / (1 + np.exp(-(a @ x)))) * a + 0.3 * x)
+    assert rel_err(sv.state.x, x) < 1e-14
+
+
+@pytest.mark.parametrize("loss", [oracle.LOGISTIC, oracle.SQUARED])
+def test_lagged_saga_has_the_dense_iterates(loss):
+    # Appendix F: deferring the dense part of each step to the next read of a
+    # coordinate changes nothing in the sequential case
+    rng = np.random.default_rng(22)
+    p = random_sparse(rng, 80, 30, 0.1, loss, 0.01)
+    dense = oracle.DenseSaga(p, seed=5)
+    lag = oracle.LaggedSaga(p, seed=5)
+    for _ in range(4):
+        dense.epochs(1)
+        lag.epochs(1)
+        assert rel_err(lag.state.x, dense.state.x) < 1e-12
+        assert rel_err(lag.state.abar, dense.state.abar) < 1e-13
+        assert rel_err(lag.state.alpha, dense.state.alpha) < 1e-12
