@@ -267,7 +267,9 @@ int asaga_epochs(asaga_ctx* ctx, int64_t n_epochs);
  * validation check has met the tolerance. */
 int asaga_set_active(asaga_ctx* ctx, const uint8_t* active);
 
-/* Apply `count` samples (single-instance contexts only). */
+/* Apply `count` samples (single-instance contexts only).  With
+ * ASAGA_METHOD_SVRG, `count` iterations, the full-gradient ones included
+ * (an epoch is n iterations either way). */
 int asaga_updates(asaga_ctx* ctx, int64_t count);
 
 /* f(x) in FP64 (Section 4.1 objective, pairwise-summed).  x_host = NULL

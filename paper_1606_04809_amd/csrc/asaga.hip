@@ -81,8 +81,8 @@ struct asaga_ctx {
     std::vector<InstArgs> plan_h;
     std::vector<BlockMap> plan_map;
     // batched step law: gamma_k = rule_k * min(step_cap, step_groups / G_k),
-    // G_k the lane groups serving instance k (0: not calibrated, use the
-    // single-instance default at 8 wavefronts per compute unit)
+    // G_k the lane groups serving instance k (0: not calibrated, use
+    // kStepGroups, the single-instance default)
     double step_groups = 0.0, step_cap = 1.0;
     // batched: captured epochs, keyed by epochs per replay, tier interval, grid
     hipStream_t cap = nullptr;

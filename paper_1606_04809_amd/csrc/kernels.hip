@@ -7,10 +7,11 @@
 // product and the scalar gradient change delta = phi'(z) - alpha_i, and adds
 // its update to x, abar and alpha_i with atomic additions (Property 3).
 //
-// Mapping to CDNA4 (64-wide wavefronts).  Measured on MI355X: the L2 atomic
-// unit serves about 2.3e10 requests/s, where one request is one wave
-// instruction's lanes that fall in one 64-byte line (up to 8 FP64 adds), and
-// a single address takes at most 8.3e7 atomics/s.  Hence:
+// Mapping to CDNA4 (64-wide wavefronts).  Measured on MI355X: FP64 global
+// atomics execute at the memory side, which serves about 2.3e10 requests/s,
+// where one request is one wave instruction's lanes that fall in one 64-byte
+// line (up to 8 FP64 adds), and a single address takes at most 8.3e7
+// atomics/s.  Hence:
 //   * a group of G lanes (64, 32, 16 or 8) owns one sample; the sample index
 //     comes from a counter-based stream, so no queue or global counter, and
 //     the next sample's row bounds are fetched while the current one runs;
@@ -20,9 +21,9 @@
 //     lane carries x_c, the odd lane abar_c.  x and abar are interleaved per
 //     column (16 bytes), so the pair's load and the pair's atomic add are
 //     each one memory request;
-//   * the row's column indices and values stream in coalesced and are read
-//     again (from cache) in the write phase instead of being held in
-//     registers, so that many wavefronts fit on a CU;
+//   * rows of up to 2G entries keep their column indices, values and state
+//     in registers between the read and the write phase; longer rows are
+//     processed in chunks and read again;
 //   * columns are relabelled by descending count, so the most-used columns
 //     are [0, H).  Each workgroup keeps them in LDS: a view of the global
 //     values and its own pending additions (LDS atomics run at ~1e12/s).
@@ -30,10 +31,13 @@
 //     global state with line-coalesced atomics and refreshes the touched
 //     part of the view from the values those atomics return; the first tier
 //     of hot columns (those nearly every row touches) is flushed every
-//     round, the rest of the hot set every few rounds.  Reads of hot columns touch only LDS;
-//     this removes the per-line serialisation of the columns every row
-//     touches, and the L2 tag stalls of reading lines with atomics in
-//     flight (atomics execute at the memory side on MI355X).
+//     round, the rest of the hot set every few rounds.  Reads of hot columns
+//     touch only LDS; this removes the per-line serialisation of the columns
+//     every row touches, and the tag stalls of reading lines with atomics in
+//     flight.
+// The same kernels run the inner steps of sparse SVRG (Appendix C) with the
+// memory frozen (InstArgs::frozen: no abar or alpha writes), and can log a
+// sample of updates' read and completion clocks (InstArgs::tau_log).
 // There is no matrix-core work: the update is a sparse gather/scatter.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
