@@ -109,6 +109,64 @@ def test_degenerate_shapes():
         assert np.all(g.get_x()[cnt == 0] == 0.0)
 
 
+def test_column_space_near_the_maximum():
+    """d above 2^26 (the state is 16 bytes per column; offsets stay below
+    2^31 up to the documented d < 2^27): rows reach the last columns, serial
+    iterates match the oracle, and the asynchronous mode with a hot set runs
+    over the whole range."""
+    rng = np.random.default_rng(8)
+    n, d = 3000, (1 << 26) + 3
+    k = rng.integers(3, 40, size=n)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(k, out=rowptr[1:])
+    cols = []
+    for kk in k:     # a few hot low columns, the rest spread to the top of the range
+        c = np.unique(np.concatenate([rng.integers(0, 64, size=2), rng.integers(0, d, size=int(kk) - 3), [d - 1]]))
+        cols.append(c)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum([len(c) for c in cols], out=rowptr[1:])
+    colidx = np.concatenate(cols).astype(np.int32)
+    val = rng.standard_normal(len(colidx))
+    val /= np.repeat(np.sqrt(np.add.reduceat(val * val, rowptr[:-1])), np.diff(rowptr))
+    b = np.where(rng.random(n) < 0.5, 1.0, -1.0)
+    p = datagen.Problem("wide", n, d, rowptr, colidx, val, b, datagen.LOGISTIC, 1.0 / n)
+    compare_serial(p, 2, per_epoch=False)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=64) as g:
+        g.epochs(3)
+        x = g.get_x()
+        assert x[d - 1] != 0.0 and np.isfinite(x).all()
+        f = g.objective()
+        assert f == pytest.approx(oracle.SparseSaga(p).objective(x), rel=1e-12)
+
+
+def test_calls_in_the_wrong_context_fail_cleanly():
+    p = datagen.config1(n=400, d=120, k=12)
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL) as g:
+        for call in (lambda: g.set_active([1]), lambda: g.autotune(), lambda: g.overlap(1)):
+            with pytest.raises(A.AsagaError) as ei:
+                call()
+            assert ei.value.code == A.ASAGA_E_STATE
+        x0 = g.get_x()
+        g.widen()                       # FP64 context: nothing to widen
+        assert np.array_equal(g.get_x(), x0)
+        g.epochs(1)                     # and the context still works
+    row_fold = datagen.folds5(p.n)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=8, batch=(row_fold, np.array([0, 1], np.int32),
+                                                                     np.array([1e-3, 1e-2]))) as g:
+        for call in (lambda: g.overlap(1), lambda: g.updates(10), lambda: g.autotune()):
+            with pytest.raises(A.AsagaError) as ei:
+                call()
+            assert ei.value.code == A.ASAGA_E_STATE
+        with pytest.raises(A.AsagaError) as ei:
+            g.set_active(np.array([1, 2], np.uint8))
+        assert ei.value.code == A.ASAGA_E_ARG
+        with pytest.raises(ValueError):
+            g.set_active([1])
+        with pytest.raises(A.AsagaError) as ei:
+            g.objective(5)
+        assert ei.value.code == A.ASAGA_E_ARG
+
+
 def test_objective_and_gradient_match_oracle():
     rng = np.random.default_rng(0)
     for p in (datagen.config1(), datagen.config3(n=20_000), ragged_problem(), datagen.config2(n=7000, d=4700)):
