@@ -259,7 +259,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on exactly one GPU (the asynchronous solve of one instance lives in one "
+        print("bench.py runs on exactly one GPU (the asynchronous solve of one instance lives in one "
               "device's memory); --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
