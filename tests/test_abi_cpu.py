@@ -173,3 +173,14 @@ def test_batched_svrg_is_rejected():
         A.Solver(**kw, mode=A.ASAGA_MODE_ASYNC, method=A.ASAGA_METHOD_SVRG,
                  batch=(np.zeros(3, np.int8), np.array([-1], np.int32), np.array([0.1])))
     assert ei.value.code == A.ASAGA_E_ARG
+
+
+def test_header_compiles_as_plain_c(tmp_path):
+    # the public header and a caller of it are plain C99 (no C++ or HIP types),
+    # and such a caller links against the library with the system C toolchain
+    pkg = os.path.join(ROOT, "paper_1606_04809_amd")
+    obj, exe = tmp_path / "driver.o", tmp_path / "driver"
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+                           "-c", os.path.join(ROOT, "tests", "abi_driver.c"), "-o", str(obj)])
+    subprocess.check_call(["gcc", str(obj), "-o", str(exe), "-L", pkg, "-lasaga", "-Wl,-rpath," + pkg])
+    assert exe.exists()
