@@ -113,8 +113,8 @@ def batched_leg(args, dev, stream):
     replayed from a captured hipGraph, mixed precision (FP32 x and alpha,
     FP64 abar, bfloat16 values), autotuned wavefronts per instance and step;
     each instance is switched off once it is within 1e-9 of its certified
-    optimum.  Then the same instances one by one with the plain FP64 async
-    kernel.  Times are kernel times between HIP events; the objective checks
+    optimum.  Then the same batch with FP64 state (still bfloat16 values),
+    and the same instances one by one with the plain FP64 async kernel.  Times are kernel times between HIP events; the objective checks
     between them are not counted."""
     import numpy as np
     import torch
@@ -144,45 +144,56 @@ def batched_leg(args, dev, stream):
 
     arrs = [to_dev(p.rowptr), to_dev(p.colidx), to_dev(p.val_bf16.view(np.int16)), to_dev(p.b)]
     torch.cuda.synchronize()
-    g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
-                 precision=A.ASAGA_PREC_MIXED, stream=stream, batch=(B.row_fold, B.inst_fold, B.inst_lambda))
-    t = time.time()
-    log("batched autotune: probing wavefronts per instance, hot-set size and step")
-    rep = g.autotune(target=1e-9, probe_epochs=6)
-    tune = {"candidates": rep.candidates, "waves_per_instance": rep.waves, "hot_columns": rep.hot_columns,
-            "gamma_inst0": rep.gamma, "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs,
-            "tuning_wall_s": time.time() - t}
-    log(f"batched autotune: {tune}")
     m = np.array([int(np.sum(B.row_fold != f)) for f in B.inst_fold])
-    active = np.ones(ni, dtype=np.uint8)
-    rel = np.full(ni, np.inf)
-    reached_at = np.zeros(ni)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    kernel_s, epochs, updates, check = 0.0, 0, 0, 3
-    while active.any() and epochs < 600:
-        e0.record(stream)
-        g.epochs(check)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        kernel_s += e0.elapsed_time(e1) / 1e3
-        updates += check * int(np.sum(m[active == 1]))
-        epochs += check
-        for k in np.nonzero(active)[0]:
-            rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
-            if rel[k] <= 1e-9:
-                active[k] = 0
-                reached_at[k] = epochs
-        g.set_active(active)
-        log(f"batched: {epochs} epochs, {int(active.sum())} instances still active, kernel {kernel_s:.3f} s")
-    g.close()
-    del arrs
+
+    def run_batched(precision, label):
+        g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
+                     precision=precision, stream=stream, batch=(B.row_fold, B.inst_fold, B.inst_lambda))
+        t = time.time()
+        log(f"batched {label}: autotune probing wavefronts per instance, hot-set size and step")
+        rep = g.autotune(target=1e-9, probe_epochs=6)
+        tune = {"candidates": rep.candidates, "waves_per_instance": rep.waves, "hot_columns": rep.hot_columns,
+                "gamma_inst0": rep.gamma, "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs,
+                "tuning_wall_s": time.time() - t}
+        log(f"batched {label} autotune: {tune}")
+        active = np.ones(ni, dtype=np.uint8)
+        rel = np.full(ni, np.inf)
+        reached_at = np.zeros(ni)
+        kernel_s, epochs, updates, check = 0.0, 0, 0, 3
+        while active.any() and epochs < 600:
+            e0.record(stream)
+            g.epochs(check)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            kernel_s += e0.elapsed_time(e1) / 1e3
+            updates += check * int(np.sum(m[active == 1]))
+            epochs += check
+            for k in np.nonzero(active)[0]:
+                rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
+                if rel[k] <= 1e-9:
+                    active[k] = 0
+                    reached_at[k] = epochs
+            g.set_active(active)
+            log(f"batched {label}: {epochs} epochs, {int(active.sum())} instances still active, "
+                f"kernel {kernel_s:.3f} s")
+        g.close()
+        return {"instances": ni, "reached": int(np.sum(rel <= 1e-9)), "epochs_max": epochs,
+                "epochs_median": float(np.median(reached_at[reached_at > 0])) if np.any(reached_at > 0) else None,
+                "seconds_to_1e-9_all": kernel_s, "updates": updates, "updates_per_s": updates / kernel_s,
+                "worst_rel_subopt": float(np.max(rel)), "autotune": tune}
+
     out = {"workload": "config5: 32 lambdas (1e-8..1e-2) x 5 uneven folds over the bfloat16 config-2 matrix, "
-                       "mixed precision (FP32 x/alpha, FP64 abar), one persistent kernel per epoch from a hipGraph",
-           "instances": ni, "reached": int(np.sum(rel <= 1e-9)), "epochs_max": epochs,
-           "epochs_median": float(np.median(reached_at[reached_at > 0])) if np.any(reached_at > 0) else None,
-           "seconds_to_1e-9_all": kernel_s, "updates": updates, "updates_per_s": updates / kernel_s,
-           "worst_rel_subopt": float(np.max(rel)), "autotune": tune}
+                       "mixed precision (FP32 x/alpha, FP64 abar), one persistent kernel per epoch from a hipGraph"}
+    out.update(run_batched(A.ASAGA_PREC_MIXED, "mixed"))
     log(f"batched: {out}")
+    if args.batched_f64_state:
+        # the same batch with FP64 x and alpha (values still bfloat16): one
+        # atomic request per lane pair instead of two
+        out["f64_state"] = run_batched(A.ASAGA_PREC_F64, "FP64 state")
+        out["f64_state"]["workload"] = "the same batch, FP64 x/alpha/abar, bfloat16 values"
+        log(f"batched FP64 state: {out['f64_state']}")
+    del arrs
 
     # the same instances one by one: plain FP64 async kernel, library defaults
     sel = np.unique(np.linspace(0, ni - 1, max(1, min(args.plain_instances, ni))).round().astype(int))
@@ -218,7 +229,7 @@ def batched_leg(args, dev, stream):
         "seconds_to_1e-9_all_160_est": plain_s * scale, "updates_per_s": plain_updates / plain_s,
         "epochs_median": float(np.median(plain_epochs)), "epochs_max": int(np.max(plain_epochs)),
         "kernel": "plain FP64 async (k_update, library default shape and step), one instance at a time"}
-    out["batched_speedup_vs_plain"] = plain_s * scale / kernel_s
+    out["batched_speedup_vs_plain"] = plain_s * scale / out["seconds_to_1e-9_all"]
     log(f"plain one by one: {out['plain_one_by_one']}")
     return out
 
@@ -252,6 +263,8 @@ def main():
     ap.add_argument("--tau-sweep", action="store_true",
                     help="add the overlap sweep: samples in flight (measured) and epochs to 1e-9 at a fixed step "
                          "versus wavefronts in flight")
+    ap.add_argument("--no-batched-f64-state", dest="batched_f64_state", action="store_false",
+                    help="omit the batched run with FP64 state (the mixed-precision batched run stays)")
     ap.add_argument("--plain-instances", type=int, default=160,
                     help="instances of the batch also solved one by one with the plain FP64 kernel (spread "
                          "evenly over the 160)")

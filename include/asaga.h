@@ -157,7 +157,10 @@ typedef struct asaga_opts {
                                  workgroups serving the instance): a hot
                                  column's LDS view is refreshed only when the
                                  workgroup next writes it, which delays its
-                                 regulariser step by about W of its updates   */
+                                 regulariser step by about W of its updates.
+                                 Where gamma 3L W D_v exceeds
+                                 4.8e4, the view is also reloaded at every
+                                 full flush (asaga_info.hot_reload_from)      */
     int32_t flush_every;      /* async: samples each lane group applies between
                                  two flushes of those combined writes
                                  (0 = automatic)                                  */
@@ -215,7 +218,10 @@ typedef struct asaga_info {
     int32_t threads_per_block;
     int32_t hot_tier_columns;
     int32_t hot_tier_every;
-    int32_t reserved;
+    int32_t hot_reload_from; /* first hot column whose LDS view each workgroup
+                                reloads at every full flush (hot_columns: none);
+                                instance 0, at the launch shape of the next
+                                asaga_epochs call (batched: of the last one)   */
 } asaga_info;
 
 /* What asaga_autotune measured and chose. */

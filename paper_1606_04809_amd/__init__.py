@@ -102,7 +102,7 @@ class asaga_info(ctypes.Structure):
                 ("lanes_per_sample", ctypes.c_int32), ("n_inst", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
                 ("flush_every", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
                 ("hot_tier_columns", ctypes.c_int32), ("hot_tier_every", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("hot_reload_from", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

@@ -250,6 +250,7 @@ InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
     a.count = count;
     a.blocks = 0;
     a.frozen = 0;
+    a.reload_from = kNoReload;
     a.tau_log = nullptr;
     a.tau_count = nullptr;
     a.tau_cap = 0;
@@ -416,6 +417,35 @@ int stable_hot(const asaga_ctx* c, const Inst& I, int hot, double workgroups) {
         else hi = mid;
     }
     return (int)lo;
+}
+
+// The first hot column whose LDS view a workgroup reloads at each full
+// flush.  A workgroup refreshes its view of a hot column when it writes the
+// column, about once in 1/(p_v s) rounds for a column of probability p_v (s
+// samples per round), while the W workgroups serving the instance apply
+// about W of its updates: the view lags by about W D_v samples (D_v = m /
+// cnt_v), and the data term's step reads it.  Measured on the RCV1-shaped
+// matrix, hot set of 4096 columns (D_v up to about 600), with rule = 1/(3L):
+// (gamma / rule) W D_v = 0.25 * 256 * 593 = 3.8e4 converges like no hot set;
+// 1.0 * 128 * 593 = 7.6e4 (a lambda = 1e-8 instance of the lambda path)
+// stalls near 2e-3 until those views are reloaded.  Columns with
+// (gamma / rule) W D_v above 4.8e4 are reloaded; the reload costs one memory
+// request per 4 columns and flush.
+constexpr double kViewLag = 49152.0;
+
+int view_reload_from(const Inst& I, int hot, double workgroups) {
+    if (hot <= 0 || !I.cnt_pmin || !(I.L > 0.0)) return kNoReload;
+    const double s = I.gamma * 3.0 * I.L * workgroups;  // (gamma / (1 / 3L)) W
+    if (!(s > 0.0)) return kNoReload;
+    const double need = (double)I.m * s / kViewLag;  // reload the columns with cnt_v < need
+    const auto& pm = *I.cnt_pmin;
+    int64_t lo = 0, hi = std::min<int64_t>(hot, (int64_t)pm.size());
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if ((double)pm[mid] >= need) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < hot ? (int)lo : kNoReload;
 }
 
 // Rounds between flushes of the second hot tier.  A column of that tier is
@@ -802,6 +832,7 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     S.tier_every = tier_every_from(c, glg);
     for (size_t k : act) S.hot = stable_hot(c, c->inst[k], S.hot, (double)blocks[k]);
     S.tier = std::min(S.tier, S.hot);
+    for (size_t k : act) h[k].reload_from = view_reload_from(c->inst[k], S.hot, (double)blocks[k]);
     *Sout = S;
     if ((int64_t)n_blocks > c->map_cap)
         return fail(c, ASAGA_E_STATE, "batched launch needs " + std::to_string(n_blocks) +
@@ -922,6 +953,7 @@ int asaga_updates(asaga_ctx* c, int64_t count) {
         }
         InstArgs a = inst_args(I, (uint64_t)I.t, (uint64_t)k);
         a.frozen = c->svrg ? 1 : 0;
+        if (!S.serial) a.reload_from = view_reload_from(I, S.hot, (double)((S.waves * 64 + S.block - 1) / S.block));
         if (c->tau_on) {
             a.tau_log = c->d_tau;
             a.tau_count = c->d_tau_count;
@@ -1676,7 +1708,15 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->threads_per_block = c->shape.block;
     out->hot_tier_columns = c->shape.tier;
     out->hot_tier_every = c->shape.serial ? c->shape.tier_every : tier_every_for(c, c->shape);
-    out->reserved = 0;
+    out->hot_reload_from = out->hot_columns;
+    if (!c->shape.serial && !c->d_insts) {
+        const double w = (double)((c->shape.waves * 64 + c->shape.block - 1) / c->shape.block);
+        const int hot = stable_hot(c, I, c->shape.hot, w);
+        const int rf = view_reload_from(I, hot, w);
+        if (rf < hot) out->hot_reload_from = rf;
+    } else if (c->d_insts && !c->plan_h.empty() && c->plan_h[0].reload_from < out->hot_columns) {
+        out->hot_reload_from = c->plan_h[0].reload_from;
+    }
     return ASAGA_OK;
 }
 

@@ -31,6 +31,9 @@ struct InstArgs {
     int32_t blocks;       // batched: workgroups serving the instance
     int32_t frozen;       // 1: the memory (alpha, abar) is held fixed, only x is written
                           //    (the inner steps of sparse SVRG)
+    int32_t reload_from;  // hot columns [reload_from, hot) that a workgroup did not write
+                          //    are read again from global memory at each full flush
+                          //    (>= hot: none)
     // overlap log (nullptr: off): a sample whose counter hashes to 0 modulo
     // kTauEvery (an independent thinning, unrelated to which lane group or
     // round runs it) takes the next entry e = (*tau_count)++ below tau_cap and
@@ -41,6 +44,7 @@ struct InstArgs {
     uint64_t tau_cap;
 };
 constexpr uint64_t kTauEvery = 1024;
+constexpr int32_t kNoReload = 1 << 20;  // above any hot-set size
 
 // Batched launches: workgroup b serves instance inst, as its rank-th
 // workgroup (inst < 0: idle).

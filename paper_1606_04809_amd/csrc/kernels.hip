@@ -31,7 +31,9 @@
 //     global state with line-coalesced atomics and refreshes the touched
 //     part of the view from the values those atomics return; the first tier
 //     of hot columns (those nearly every row touches) is flushed every
-//     round, the rest of the hot set every few rounds.  Reads of hot columns
+//     round, the rest of the hot set every few rounds, when the untouched
+//     views of the rarest hot columns are reloaded too if the host finds
+//     their lag too long for the step.  Reads of hot columns
 //     touch only LDS; this removes the per-line serialisation of the columns
 //     every row touches, and the tag stalls of reading lines with atomics in
 //     flight.
@@ -300,14 +302,29 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
     if constexpr (SERIAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 
+// The global value of slot q of the interleaved state (x in FP32 for the
+// mixed layout), read at the device-coherent level.
+template <bool MIXED>
+__device__ __forceinline__ double load_slot(const double* xa, int q) {
+    if (MIXED && (q & 1) == 0)
+        return (double)__hip_atomic_load(reinterpret_cast<float*>(const_cast<double*>(xa) + q), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(const_cast<double*>(xa) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Add the workgroup's pending sums of hot columns [0, upto) to the global
 // state and clear them.  A slot with a pending sum takes, as its new view, the
 // value its returning atomic add reports plus the sum (the global value
-// including every flush so far); untouched slots keep their view until the
-// workgroup next writes them.  Consecutive threads take consecutive slots,
-// so each wave instruction covers 512 contiguous bytes (8 lines).
+// including every flush so far).  Every other slot of a column at or above
+// `reload_from` reads its global value again; the rest keep their view until
+// the workgroup next writes them.  (A workgroup writes a hot column of
+// probability p_v about once in 1/(p_v * samples per round) rounds, while the
+// other workgroups apply about W of its updates, each a step of about
+// gamma D_v: without a reload, the view of the rarer hot columns lags by
+// about W D_v samples.)  Consecutive threads take consecutive slots, so each
+// wave instruction covers 512 contiguous bytes (8 lines).
 template <bool MIXED>
-__device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto) {
+__device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto, int reload_from) {
     for (int q = threadIdx.x; q < 2 * upto; q += blockDim.x) {
         const double w = lds[2 * hot + q];
         if (w != 0.0) {
@@ -319,6 +336,8 @@ __device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto)
                 now = __hip_atomic_fetch_add(xa + q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + w;
             lds[q] = now;
             lds[2 * hot + q] = 0.0;
+        } else if (q >= 2 * reload_from) {
+            lds[q] = load_slot<MIXED>(xa, q);
         }
     }
 }
@@ -326,13 +345,7 @@ __device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto)
 template <bool MIXED>
 __device__ __forceinline__ void load_view(const double* xa, int hot) {
     for (int q = threadIdx.x; q < 2 * hot; q += blockDim.x) {
-        double now;
-        if (MIXED && (q & 1) == 0)
-            now = (double)__hip_atomic_load(reinterpret_cast<float*>(const_cast<double*>(xa) + q), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-        else
-            now = __hip_atomic_load(const_cast<double*>(xa) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        lds[q] = now;
+        lds[q] = load_slot<MIXED>(xa, q);
         lds[2 * hot + q] = 0.0;
     }
 }
@@ -342,8 +355,9 @@ __device__ __forceinline__ void load_view(const double* xa, int hot) {
 // The row bounds of the next sample are fetched while the current one is
 // processed.  With a hot set, all groups of the workgroup advance in rounds
 // of `flush` samples; after each round the workgroup flushes the first
-// `tier` hot columns, and all hot columns every `tier_every` rounds and at
-// the end of the launch.
+// `tier` hot columns, and all hot columns every `tier_every` rounds (then
+// reloading the view of the slots from `reload_from` on that it did not
+// write) and at the end of the launch.
 template <int G, int P, bool SERIAL, bool RACY, bool MIXED, typename VT>
 __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, uint64_t t0, uint64_t slot,
                                           uint64_t slots, HotArgs H, int* flag) {
@@ -387,9 +401,11 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
             cur = nxt;
         }
         if (hot > 0) {
-            const bool all = k1 == kmax || (r + 1) % (uint64_t)H.tier_every == 0;
+            const bool last = k1 == kmax;
+            const bool all = last || (r + 1) % (uint64_t)H.tier_every == 0;
             __syncthreads();
-            flush_and_refresh<MIXED>(I.xa, hot, all ? hot : H.tier);
+            const int upto = all ? hot : H.tier;
+            flush_and_refresh<MIXED>(I.xa, hot, upto, all && !last && I.reload_from < upto ? I.reload_from : upto);
             __syncthreads();
         }
     }
