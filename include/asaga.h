@@ -165,11 +165,12 @@ typedef struct asaga_opts {
                                  two flushes of those combined writes
                                  (0 = automatic)                                  */
     int32_t threads_per_block;/* async: workgroup size, a multiple of 64 up to
-                                 1024 (0 = automatic: 512).  A workgroup shares
-                                 one hot set, so larger ones need fewer flush
-                                 requests per sample, but one workgroup per
-                                 compute unit then puts more samples in
-                                 flight, which lowers the stable step          */
+                                 1024 (0 = automatic: 512, batches 1024).  A
+                                 workgroup shares one hot set, so larger ones
+                                 need fewer flush requests per sample, but one
+                                 workgroup per compute unit then puts more
+                                 samples in flight, which lowers the stable
+                                 step                                          */
     int32_t hot_tier_columns; /* async: the first hot columns, flushed after every
                                  round of flush_every samples; the others are
                                  flushed every hot_tier_every rounds

@@ -394,6 +394,18 @@ int setup_instance(asaga_ctx* c, Inst& I, const Inst* same_rows) {
 // probe can no longer tell a stable step from a slowly diverging one.
 int64_t max_groups_for(int64_t m) { return std::max<int64_t>(1, m / 64); }
 
+// Automatic workgroup size.  One solve: 512 threads (a 1024-thread workgroup
+// shares one hot set and one flush among twice the samples, +52% updates/s
+// on the RCV1-shaped matrix, but doubles the samples in flight, and on the
+// lambda path the halved stable step costs more epochs than that saves).  A
+// batch: 1024, since each instance gets only the lane groups its step law
+// can use at the full step (the lambda path x folds batch of 160 instances
+// reaches 1e-9 in 6.3-6.6 s instead of 8.3-9.7 s with 512).
+int default_block(const asaga_opts& o, bool batched) {
+    if (o.threads_per_block > 0) return o.threads_per_block;
+    return batched ? 1024 : 512;
+}
+
 // A workgroup's LDS view of hot column v is refreshed when the workgroup
 // next writes v, so the column's regulariser step gamma lambda D_v x_v reads
 // a value about one of v's own updates old per workgroup serving the
@@ -501,7 +513,7 @@ void pick_shape(asaga_ctx* c) {
         lanes = p;
     }
     S.lanes = lanes;
-    S.block = c->o.threads_per_block > 0 ? c->o.threads_per_block : 512;
+    S.block = default_block(c->o, c->d_insts != nullptr);
     int waves = c->o.waves;
     if (waves == 0) {
         int cus = device_cu_count();
@@ -722,7 +734,7 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
         {
             int cus = device_cu_count();
             if (cus <= 0) cus = 256;
-            const int block = o->threads_per_block > 0 ? o->threads_per_block : 512;
+            const int block = default_block(*o, true);
             const int64_t bpi = o->waves > 0 ? ((int64_t)o->waves * 64 + block - 1) / block : 1;
             c->map_cap = std::max<int64_t>({(int64_t)c->inst.size() * bpi, (int64_t)cus * (2048 / block),
                                             (int64_t)c->inst.size()});
@@ -782,7 +794,11 @@ int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, XView* x) {
 // still running take over the workgroups of those switched off.  The step
 // of instance k without opts.step is rule_k * min(step_cap, step_groups /
 // G_k): samples in flight for an instance grow with its workgroups, and the
-// stable step shrinks in proportion (Theorem 2).
+// stable step shrinks in proportion (Theorem 2).  An instance therefore gets
+// at most step_groups / step_cap lane groups: beyond that its step shrinks
+// as fast as its samples in flight grow, and the throughput they add grows
+// more slowly than that (measured on the RCV1-shaped matrix), so the extra
+// workgroups would make it slower to reach a given accuracy.
 int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     const size_t ni = c->inst.size();
     UpdateShape S = c->shape;
@@ -802,8 +818,12 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
         const int share = std::max<int>(res, (int)act.size());
         const int q = share / (int)act.size(), r = share % (int)act.size();
         const int64_t gpb = S.block / S.lanes;  // lane groups per workgroup
+        const double sg = c->step_groups > 0.0 ? c->step_groups : kStepGroups;
+        const int64_t useful =
+            c->o.step > 0.0 ? INT64_MAX
+                            : std::max<int64_t>(1, (int64_t)std::ceil(sg / (c->step_cap * (double)gpb)));
         for (size_t a = 0; a < act.size(); ++a) {
-            const int64_t cap = std::max<int64_t>(1, max_groups_for(c->inst[act[a]].m) / gpb);
+            const int64_t cap = std::min(useful, std::max<int64_t>(1, max_groups_for(c->inst[act[a]].m) / gpb));
             blocks[act[a]] = (int)std::min<int64_t>(cap, q + ((int)a < r ? 1 : 0));
             n_blocks += blocks[act[a]];
         }
@@ -1216,7 +1236,9 @@ namespace {
 // gamma_k = rule_k * min(step_cap, step_groups / G_k) is calibrated where it
 // matters most, on the instance with the smallest lambda (the slowest, the
 // last one running) given the whole device, as a single-instance step
-// ladder; then step_cap is checked with every instance running.
+// ladder (from the single solve's default law down) with the single solve's
+// stability test, and a three times longer run of the choice; then step_cap
+// is checked with every instance running.
 int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune_report* rep) {
     if (c->o.step > 0.0) return fail(c, ASAGA_E_STATE, "batched autotuning chooses the steps: opts.step must be 0");
     if (c->o.waves > 0)
@@ -1247,18 +1269,22 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
     HIPCHK(c, hipEventCreate(&e1));
     int rc = ASAGA_OK, tried = 0;
     const int cps[3] = {probe_epochs / 3, 2 * probe_epochs / 3, probe_epochs};
-    // Run from zero with checkpoints cps; false if some active instance's
-    // ||grad f|| did not decrease at every checkpoint before it was already
-    // certified; *est_e: epochs until the slowest one reaches
-    // ||g||^2 <= 2 lambda target f at its last measured rate.
-    auto probe = [&](double* est_e) -> bool {
+    const int cps3[3] = {probe_epochs, 2 * probe_epochs, 3 * probe_epochs};
+    // Run from zero with checkpoints cp; false if some active instance was
+    // unstable before it was already certified: with `strict` (one instance
+    // alone), unless its ||grad f|| fell and its objective did not rise at
+    // every checkpoint, as for a single solve; otherwise unless ||grad f||
+    // never doubled and ended below its first value.  *est_e: epochs until
+    // the slowest one reaches ||g||^2 <= 2 lambda target f at its last
+    // measured rate.
+    auto probe = [&](const int* cp, bool strict, double* est_e) -> bool {
         if ((rc = reset_state(c))) return false;
         std::vector<double> g2(3 * ni, 0.0), f(3 * ni, 0.0), goal(ni, 0.0);
         std::vector<int> reached(ni, -1);
         int done = 0;
         for (int k = 0; k < 3; ++k) {
-            if ((rc = asaga_epochs(c, cps[k] - done))) return false;
-            done = cps[k];
+            if ((rc = asaga_epochs(c, cp[k] - done))) return false;
+            done = cp[k];
             for (size_t j = 0; j < ni; ++j) {
                 if (!c->inst[j].active || reached[j] >= 0) continue;
                 double* gj = &g2[3 * j];
@@ -1267,7 +1293,9 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
                 if (!(std::isfinite(gj[k]) && std::isfinite(f[3 * j + k]))) return false;
                 goal[j] = probe_goal(c, c->inst[j], target, f[3 * j + k], x2);
                 if (gj[k] <= goal[j]) reached[j] = k;
-                else if (probe_unstable(gj, k)) return false;
+                else if (strict ? k > 0 && !(gj[k] < gj[k - 1] && f[3 * j + k] <= f[3 * j + k - 1])
+                                : probe_unstable(gj, k))
+                    return false;
             }
         }
         int flag = 0;
@@ -1277,18 +1305,18 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             return false;
         }
         if (flag) return false;
-        double e = (double)cps[2];
+        double e = (double)cp[2];
         for (size_t j = 0; j < ni; ++j) {
             if (!c->inst[j].active || reached[j] >= 0) continue;
             const double* gj = &g2[3 * j];
-            const double ea = aitken_epochs(&f[3 * j], cps, target);
+            const double ea = aitken_epochs(&f[3 * j], cp, target);
             if (ea >= 0.0) {
                 e = std::max(e, ea);
                 continue;
             }
-            const double r = probe_rate(gj, cps);
+            const double r = probe_rate(gj, cp);
             if (r == 0.0) return false;
-            e = std::max(e, (double)cps[2] + (gj[2] > goal[j] ? 0.5 * std::log(gj[2] / goal[j]) / r : 0.0));
+            e = std::max(e, (double)cp[2] + (gj[2] > goal[j] ? 0.5 * std::log(gj[2] / goal[j]) / r : 0.0));
         }
         *est_e = e;
         return true;
@@ -1317,25 +1345,31 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         const int64_t gpb = S.block / S.lanes;
         const int64_t cal_blocks = std::min<int64_t>(res, std::max<int64_t>(1, max_groups_for(c->inst[cal].m) / gpb));
         const double groups = (double)(cal_blocks * gpb);
-        if ((rc = reset_state(c))) break;
-        hipError_t he = hipEventRecord(e0, c->st);
-        if (he == hipSuccess && (rc = batched_piece(c, 1))) break;
-        if (he == hipSuccess) he = hipEventRecord(e1, c->st);
-        if (he == hipSuccess) he = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        if (he != hipSuccess) {
-            rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
-            break;
-        }
+        // the ladder starts from the single solve's default law (measured
+        // stable on the RCV1-shaped matrix up to 4096 samples in flight):
+        // short probes from zero cannot certify a larger one, whose
+        // instability may grow only near the optimum
+        const double top = std::min(groups, kStepGroups);
         double shape_best = INFINITY;
         bool stable = false;
         for (double sc : scales) {
             ++tried;
-            c->step_groups = sc * groups;
+            c->step_groups = sc * top;
             c->step_cap = 1.0;
+            // kernel time per epoch under this law (it sets the workgroups)
+            float ms = 0.0f;
+            if ((rc = reset_state(c))) break;
+            hipError_t he = hipEventRecord(e0, c->st);
+            if (he == hipSuccess && (rc = batched_piece(c, 1))) break;
+            if (he == hipSuccess) he = hipEventRecord(e1, c->st);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) {
+                rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
+                break;
+            }
             double est_e = 0.0;
-            const bool ok = probe(&est_e);
+            const bool ok = probe(cps, true, &est_e);
             if (rc) break;
             if (!ok) {
                 if (stable) break;
@@ -1343,7 +1377,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             }
             stable = true;
             const double est_s = est_e * (double)ms * 1e-3;
-            if (est_s < best.est_s) best = Best{est_s, est_e, (double)ms, sc * groups, S};
+            if (est_s < best.est_s) best = Best{est_s, est_e, (double)ms, sc * top, S};
             // FP32 x reaches its rounding floor within a short probe whatever
             // the step, so the rates cannot rank the steps: the largest stable
             // one is kept (in the step-limited regime it converges fastest)
@@ -1351,6 +1385,30 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             shape_best = est_s;
         }
         if (rc) break;
+    }
+    // The short probes see mostly the fast early decrease, which a step at
+    // the edge of stability can still show (or not, from one run to the
+    // next): from the chosen law down the ladder, the calibration instance
+    // runs three times longer until a law passes that too.  (The instance
+    // runs on step_groups lane groups at the full step, so of two stable
+    // laws the larger is the faster.)
+    if (!rc && std::isfinite(best.est_s)) {
+        c->shape = best.S;
+        c->step_cap = 1.0;
+        drop_graphs(c);
+        const double g0 = best.groups;
+        bool ok = false;
+        for (int down = 0; down < 12 && !ok && !rc; ++down) {
+            ++tried;
+            c->step_groups = g0 * std::exp2(-(double)down / 3.0);
+            double est_e = 0.0;
+            ok = probe(cps3, true, &est_e);
+            if (ok) {
+                best.groups = c->step_groups;
+                best.est_e = est_e;
+            }
+        }
+        if (!ok && !rc) best.est_s = INFINITY;
     }
     // 2. every instance running: the largest stable cap
     double cap = 0.0;
@@ -1363,7 +1421,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             ++tried;
             c->step_cap = cp;
             double est_e = 0.0;
-            const bool ok = probe(&est_e);
+            const bool ok = probe(cps, false, &est_e);
             if (rc) break;
             if (ok) {
                 cap = cp;
