@@ -154,8 +154,8 @@ def batched_leg(args, dev, stream):
         log(f"batched {label}: autotune probing wavefronts per instance, hot-set size and step")
         rep = g.autotune(target=1e-9, probe_epochs=6)
         tune = {"candidates": rep.candidates, "waves_per_instance": rep.waves, "hot_columns": rep.hot_columns,
-                "gamma_inst0": rep.gamma, "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs,
-                "tuning_wall_s": time.time() - t}
+                "gamma_inst0": rep.gamma, "step_groups": rep.step_groups, "step_cap": rep.step_cap,
+                "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs, "tuning_wall_s": time.time() - t}
         log(f"batched {label} autotune: {tune}")
         active = np.ones(ni, dtype=np.uint8)
         rel = np.full(ni, np.inf)

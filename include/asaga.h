@@ -235,6 +235,11 @@ typedef struct asaga_tune_report {
     double ms_per_epoch;      /* measured kernel time per epoch at the choice       */
     double est_epochs;        /* estimated epochs from a cold start to the target   */
     double est_seconds;       /* estimated kernel seconds to the target             */
+    double step_groups;       /* batches: the step law gamma_k = rule_k * min(step_cap,
+                                 step_groups / G_k), G_k the lane groups serving
+                                 instance k (at most step_groups / step_cap);
+                                 one solve: 0                                      */
+    double step_cap;
 } asaga_tune_report;
 
 /* Create a context: validate the problem, copy host arrays to the device

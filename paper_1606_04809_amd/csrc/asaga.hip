@@ -799,6 +799,23 @@ int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, XView* x) {
 // as fast as its samples in flight grow, and the throughput they add grows
 // more slowly than that (measured on the RCV1-shaped matrix), so the extra
 // workgroups would make it slower to reach a given accuracy.
+// workgroups an instance of a batch can use under the step law (no limit
+// with a fixed step)
+int64_t useful_blocks(const asaga_ctx* c, const UpdateShape& S) {
+    if (c->o.step > 0.0) return INT64_MAX;
+    const double sg = c->step_groups > 0.0 ? c->step_groups : kStepGroups;
+    const double gpb = (double)(S.block / S.lanes);
+    return std::max<int64_t>(1, (int64_t)std::ceil(sg / (c->step_cap * gpb)));
+}
+
+// workgroups per instance of a batch with automatic waves when n_act
+// instances are active (the plan's equal share, before the m/64 bound)
+int64_t batched_share(const asaga_ctx* c, const UpdateShape& S, int n_act) {
+    int res = batched_resident_blocks(S, c->val_dtype);
+    if (res <= 0) res = std::max(1, device_cu_count());
+    return std::min<int64_t>(useful_blocks(c, S), std::max(1, res / std::max(1, n_act)));
+}
+
 int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     const size_t ni = c->inst.size();
     UpdateShape S = c->shape;
@@ -818,10 +835,7 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
         const int share = std::max<int>(res, (int)act.size());
         const int q = share / (int)act.size(), r = share % (int)act.size();
         const int64_t gpb = S.block / S.lanes;  // lane groups per workgroup
-        const double sg = c->step_groups > 0.0 ? c->step_groups : kStepGroups;
-        const int64_t useful =
-            c->o.step > 0.0 ? INT64_MAX
-                            : std::max<int64_t>(1, (int64_t)std::ceil(sg / (c->step_cap * (double)gpb)));
+        const int64_t useful = useful_blocks(c, S);
         for (size_t a = 0; a < act.size(); ++a) {
             const int64_t cap = std::min(useful, std::max<int64_t>(1, max_groups_for(c->inst[act[a]].m) / gpb));
             blocks[act[a]] = (int)std::min<int64_t>(cap, q + ((int)a < r ? 1 : 0));
@@ -1446,16 +1460,18 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
     UpdateShape S;
     if ((rc = plan_batched(c, &S))) return rc;  // sets every instance's step for the full batch
     if (rep) {
-        int n_act = 0, res = batched_resident_blocks(S, c->val_dtype);
+        int n_act = 0;
         for (size_t k = 0; k < ni; ++k) n_act += c->inst[k].active ? 1 : 0;
         rep->candidates = tried;
-        rep->waves = std::max(1, res / std::max(1, n_act)) * (S.block / 64);
+        rep->waves = (int32_t)batched_share(c, S, n_act) * (S.block / 64);
         rep->hot_columns = S.hot;
         rep->hot_tier_columns = S.tier;
         rep->gamma = c->inst[0].gamma;
         rep->ms_per_epoch = best.ms;
         rep->est_epochs = best.est_e;
         rep->est_seconds = best.est_s;
+        rep->step_groups = c->step_groups;
+        rep->step_cap = c->step_cap;
     }
     return ASAGA_OK;
 }
@@ -1639,6 +1655,8 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         rep->ms_per_epoch = best.ms;
         rep->est_epochs = best.est_e;
         rep->est_seconds = best.est_s;
+        rep->step_groups = 0.0;
+        rep->step_cap = 0.0;
     }
     return ASAGA_OK;
 }
@@ -1755,9 +1773,9 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->lambda = I.lambda;
     out->waves = c->shape.waves;
     if (c->d_insts && c->o.waves == 0) {
-        int n_act = 0, res = batched_resident_blocks(c->shape, c->val_dtype);
+        int n_act = 0;
         for (const Inst& J : c->inst) n_act += J.active ? 1 : 0;
-        out->waves = std::max(1, res / std::max(1, n_act)) * (c->shape.block / 64);
+        out->waves = (int32_t)batched_share(c, c->shape, n_act) * (c->shape.block / 64);
     }
     out->lanes_per_sample = c->shape.lanes;
     out->n_inst = (int32_t)c->inst.size();

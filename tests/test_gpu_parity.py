@@ -422,6 +422,27 @@ def test_batched_instances_reach_their_own_optimum():
             assert rel_err(abar, oracle.SparseSaga(sub).memory_average(alpha)) < 1e-11
 
 
+def test_batched_instance_gets_only_the_lane_groups_its_step_law_uses():
+    """Automatic waves in a batch: the step law rule * min(cap, c / G) stops
+    growing with G at G = c / cap, so an instance gets at most that many lane
+    groups (the default law: c = 512 at cap 1) however few instances share
+    the device, and runs at the full serial step; with a fixed step it gets
+    its share of the device."""
+    p = datagen.config2(n=200_000, d=5000)   # m/64 = 2500 > 512 lane groups
+    row_fold = datagen.folds5(p.n, seed=0)
+    batch = (row_fold, np.array([0], dtype=np.int32), np.array([1e-4]))
+    sub = datagen.subproblem(p, np.nonzero(row_fold != 0)[0], lam=1e-4)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, batch=batch) as g:
+        g.epochs(1)
+        info = g.info()
+        assert info.threads_per_block == 1024
+        assert info.waves * 64 // info.lanes_per_sample == 512
+        assert info.gamma == pytest.approx(oracle.SparseSaga(sub).gamma, rel=1e-14)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, batch=batch, step=0.1) as g:
+        info = g.info()
+        assert info.waves * 64 // info.lanes_per_sample > 512
+
+
 def small_batch(n=12_000, d=3000, lams=(1e-4, 1e-3), folds=(0, 3)):
     p = datagen.config2(n=n, d=d)
     row_fold = datagen.folds5(p.n, seed=0)
