@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SAGA updates/s + HBM GB/s; time to 1e-9 rel. subopt., plain vs batched"
 HBM_PEAK_GBPS = 8000.0
 PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "k_update_config2_pmc.txt")
+REQUEST_SUMMARY = os.path.join(ROOT, "profiles", "k_update_config2_requests.txt")
 
 
 def log(*a):
@@ -51,12 +52,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(per_launch_updates: int):
-    """HBM bytes per launch from the committed rocprofv3 --pmc summary, or
-    None if it is missing or was taken on other kernel sources."""
+def _profile_values(path: str, per_launch_updates: int):
+    """The key: value lines of a committed rocprofv3 summary, or None if it is
+    missing or was taken on other kernel sources or another workload."""
     try:
         kv = {}
-        with open(PROFILE_SUMMARY) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line and not line.startswith("#"):
                     k, v = line.split(":", 1)
@@ -65,8 +66,34 @@ def traffic_from_profile(per_launch_updates: int):
             return None
         if int(kv["updates_per_launch"]) != per_launch_updates:
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        return kv
     except (OSError, KeyError, ValueError):
+        return None
+
+
+def traffic_from_profile(per_launch_updates: int, shape):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary (taken
+    at the benchmarked launch shape), or None."""
+    kv = _profile_values(PROFILE_SUMMARY, per_launch_updates)
+    if kv is None or shape != "benchmarked":
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def requests_from_profile(per_launch_updates: int, shape):
+    """Memory-side atomic and read requests per update at the given launch
+    shape ("benchmarked" or "library") from the committed counter summary,
+    or None."""
+    kv = _profile_values(REQUEST_SUMMARY, per_launch_updates)
+    if kv is None or shape is None:
+        return None
+    try:
+        return {"atomic_per_update": float(kv[f"{shape}_atomic_requests_per_update"]),
+                "read_per_update": float(kv[f"{shape}_read_requests_per_update"])}
+    except (KeyError, ValueError):
         return None
 
 
@@ -374,7 +401,19 @@ def main():
     bytes_per_launch = bytes_per_update * p.n
     avg_launch_s = total_ms / args.steps / 1e3
     achieved_gbps = bytes_per_launch / avg_launch_s / 1e9
-    traffic = traffic_from_profile(p.n)
+    # the launch shape the committed counter summaries were taken at, if this is one
+    if args.library_defaults:
+        prof_shape = "library"
+    elif (args.block, args.waves, args.step_scale, args.hot, args.flush, args.lanes) == (1024, 4096, 0.125, 0, 0, 0):
+        prof_shape = "benchmarked"
+    else:
+        prof_shape = None
+    traffic = traffic_from_profile(p.n, prof_shape)
+    requests = requests_from_profile(p.n, prof_shape)
+    if requests is not None:
+        # memory-side requests per second at this run's measured update rate
+        requests.update(atomic_per_s=requests["atomic_per_update"] * ups, read_per_s=requests["read_per_update"] * ups,
+                        source=os.path.relpath(REQUEST_SUMMARY, ROOT))
 
     # ---- time to 1e-9 relative suboptimality from a cold start ----------------
     def time_to_target(step, shape):
@@ -450,7 +489,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved_gbps / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_update (async, FP64)", "bytes_per_update": bytes_per_update,
-                     "launch_ms": avg_launch_s * 1e3},
+                     "launch_ms": avg_launch_s * 1e3, "memory_side_requests": requests},
         "time_to_1e-9": tta,
         "time_to_1e-9_autotuned": tta_tuned,
         "time_to_1e-9_svrg": tta_svrg,
