@@ -187,7 +187,7 @@ def batched_leg(args, dev, stream):
         active = np.ones(ni, dtype=np.uint8)
         rel = np.full(ni, np.inf)
         reached_at = np.zeros(ni)
-        kernel_s, epochs, updates, check = 0.0, 0, 0, 3
+        kernel_s, epochs, updates, check = 0.0, 0, 0, 1
         while active.any() and epochs < 600:
             e0.record(stream)
             g.epochs(check)

@@ -1366,6 +1366,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         const double top = std::min(groups, kStepGroups);
         double shape_best = INFINITY;
         bool stable = false;
+        int misses = 0;
         for (double sc : scales) {
             ++tried;
             c->step_groups = sc * top;
@@ -1386,9 +1387,10 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             const bool ok = probe(cps, true, &est_e);
             if (rc) break;
             if (!ok) {
-                if (stable) break;
+                if (stable && ++misses >= 2) break;  // one failure below a pass can be noise
                 continue;
             }
+            misses = 0;
             stable = true;
             const double est_s = est_e * (double)ms * 1e-3;
             if (est_s < best.est_s) best = Best{est_s, est_e, (double)ms, sc * top, S};
@@ -1583,7 +1585,7 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         // steps from the largest down, while the estimate improves: past the
         // best stable step, smaller steps only converge more slowly
         double shape_best = INFINITY;
-        int stable = 0;
+        int stable = 0, misses = 0;
         for (double sc : scales) {
             ++tried;
             I.gamma = serial_rule * sc;
@@ -1591,9 +1593,13 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             const bool ok = probe(cps, &est_e);
             if (rc) break;
             if (!ok) {
-                if (stable) break;
+                // below a step that passed, one failure can be noise (a step at
+                // the edge passes or fails from one run to the next); two end
+                // the ladder
+                if (stable && ++misses >= 2) break;
                 continue;
             }
+            misses = 0;
             ++stable;
             const double est_s = est_e * (double)ms * 1e-3;
             stable_cands.push_back({est_s, est_e, (double)ms, I.gamma, S});
