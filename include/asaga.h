@@ -158,9 +158,9 @@ typedef struct asaga_opts {
                                  column's LDS view is refreshed only when the
                                  workgroup next writes it, which delays its
                                  regulariser step by about W of its updates.
-                                 Where gamma 3L W D_v exceeds
-                                 4.8e4, the view is also reloaded at every
-                                 full flush (asaga_info.hot_reload_from)      */
+                                 Where gamma 3L W D_v exceeds 4.8e4, the view
+                                 is also reloaded at every full flush
+                                 (asaga_info.hot_reload_from)                 */
     int32_t flush_every;      /* async: samples each lane group applies between
                                  two flushes of those combined writes
                                  (0 = automatic)                                  */

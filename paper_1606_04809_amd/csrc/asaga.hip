@@ -786,19 +786,6 @@ int eval_x(asaga_ctx* c, int32_t inst, const double* x_host, XView* x) {
     return ASAGA_OK;
 }
 
-// Work plan of one batched launch: which workgroups serve which instance,
-// each instance's step, and the tier interval.  With opts.waves set, every
-// instance keeps waves / (waves per workgroup) workgroups.  Otherwise the
-// grid is the device's resident capacity, shared equally among the active
-// instances (each at least one workgroup), so that instances that are
-// still running take over the workgroups of those switched off.  The step
-// of instance k without opts.step is rule_k * min(step_cap, step_groups /
-// G_k): samples in flight for an instance grow with its workgroups, and the
-// stable step shrinks in proportion (Theorem 2).  An instance therefore gets
-// at most step_groups / step_cap lane groups: beyond that its step shrinks
-// as fast as its samples in flight grow, and the throughput they add grows
-// more slowly than that (measured on the RCV1-shaped matrix), so the extra
-// workgroups would make it slower to reach a given accuracy.
 // workgroups an instance of a batch can use under the step law (no limit
 // with a fixed step)
 int64_t useful_blocks(const asaga_ctx* c, const UpdateShape& S) {
@@ -816,6 +803,20 @@ int64_t batched_share(const asaga_ctx* c, const UpdateShape& S, int n_act) {
     return std::min<int64_t>(useful_blocks(c, S), std::max(1, res / std::max(1, n_act)));
 }
 
+// Work plan of one batched launch: which workgroups serve which instance,
+// each instance's step, and the tier interval.  With opts.waves set, every
+// instance keeps waves / (waves per workgroup) workgroups.  Otherwise the
+// grid is the device's resident capacity, shared equally among the active
+// instances (each at least one workgroup), so that instances that are
+// still running take over the workgroups of those switched off.  The step
+// of instance k without opts.step is rule_k * min(step_cap, step_groups /
+// G_k): samples in flight for an instance grow with its workgroups, and the
+// stable step shrinks in proportion (Theorem 2).  An instance therefore gets
+// at most step_groups / step_cap lane groups: beyond that its step shrinks
+// as fast as its samples in flight grow, while the throughput they add grows
+// more slowly (measured on the RCV1-shaped matrix), so an instance whose
+// epochs grow like 1/step (the small-lambda instances of a lambda path, the
+// last ones running) would reach a given accuracy later.
 int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     const size_t ni = c->inst.size();
     UpdateShape S = c->shape;
