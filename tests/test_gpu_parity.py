@@ -304,6 +304,60 @@ def test_hot_view_reload_with_many_workgroups(golden):
         assert rel <= 1e-9
 
 
+def test_async_config2_benchmarked_shape_reaches_1e9(golden):
+    """Config 2 in the launch configuration the benchmark times: 1024-thread
+    workgroups, 4096 wavefronts, 1/8 of the serial rule (34 epochs when
+    measured); the running average stays exact."""
+    p = datagen.config2()
+    assert p.digest() == golden["config2"]["digest"]
+    fstar = golden["config2"]["f_lower"]
+    rule = 1.0 / (3.0 * (0.25 * float(np.max(np.add.reduceat(p.val ** 2, p.rowptr[:-1]))) + p.lam))
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=4096, threads_per_block=1024, step=rule / 8) as g:
+        info = g.info()
+        assert (info.waves, info.threads_per_block, info.hot_columns) == (4096, 1024, 4096)
+        assert info.hot_reload_from == info.hot_columns
+        ep, rel = run_to(g, fstar, max_epochs=60)
+        say(f"config2 benchmarked shape: {ep} epochs, rel {rel:.2e}")
+        assert rel <= 1e-9
+        x, alpha, abar, t = g.get_state()
+        assert t == ep * p.n
+        assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-11
+
+
+def test_batched_config5_all_160_reach_1e9(golden):
+    """The lambda path x folds batch as the benchmark runs it: 160 instances
+    over the bfloat16 config-2 matrix, mixed precision, autotuned step law,
+    automatic workgroups, each switched off at 1e-9 of its certified optimum;
+    the last instances running (lambda = 1e-8) must converge too."""
+    import hashlib
+    B = datagen.config5()
+    h = hashlib.sha256(B.problem.digest().encode())
+    for a in (B.row_fold, B.inst_fold, B.inst_lambda):
+        h.update(np.ascontiguousarray(a).tobytes())
+    assert h.hexdigest() == golden["config5"]["digest"]
+    fstar = np.array([e["f_lower"] for e in sorted(golden["config5"]["instances"], key=lambda e: e["k"])])
+    ni = B.n_inst
+    with A.from_problem(B.problem, bf16=True, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED,
+                        batch=(B.row_fold, B.inst_fold, B.inst_lambda)) as g:
+        rep = g.autotune(target=1e-9, probe_epochs=6)
+        say(f"config5 autotune: step law c = {rep.step_groups:.0f}, cap = {rep.step_cap}, hot {rep.hot_columns}")
+        active = np.ones(ni, dtype=np.uint8)
+        rel = np.full(ni, np.inf)
+        ep = 0
+        while active.any() and ep < 200:
+            g.epochs(3)
+            ep += 3
+            for k in np.nonzero(active)[0]:
+                rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
+            active[rel <= 1e-9] = 0
+            g.set_active(active)
+            if ep % 30 == 0:
+                say(f"config5 batched: {ep} epochs, {int(active.sum())} instances still active")
+        say(f"config5 batched: {ep} epochs, worst rel {np.max(rel):.2e}")
+        assert np.all(rel <= 1e-9)
+        assert np.all(rel >= -1e-11)
+
+
 def run_to(g, fstar, target=1e-9, max_epochs=400, every=1):
     """Epochs until (f - f*)/f* <= target; returns (epochs, rel)."""
     ep, rel = 0, np.inf
