@@ -11,12 +11,13 @@ Prints one JSON line: updates/s, algorithmic HBM GB/s against the 8 TB/s
 roofline (per-launch time measured with HIP events on the library's
 stream), the time to 1e-9 relative suboptimality from a cold start, the
 batched leg (160 lambda x fold instances over the same matrix in bfloat16,
-mixed precision, to 1e-9 each, against the same instances solved one by
-one with the plain FP64 kernel), and the CPU oracle timed on a bounded
-sample on this host.
+mixed precision and again with FP64 state, to 1e-9 each, against the same
+instances solved one by one with the plain FP64 kernel), and the CPU oracle
+timed on a bounded sample on one pinned core of this host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-tta]
-                    [--skip-batched] [--plain-instances N] [--copy-calibration]
+                    [--skip-batched] [--no-batched-f64-state] [--plain-instances N]
+                    [--library-defaults] [--tau-sweep] [--copy-calibration]
 
 --copy-calibration adds a plain 1 GiB device-to-device copy (known bytes
 read and written) so that a profiler's per-dispatch byte counters can be
@@ -41,6 +42,18 @@ REQUEST_SUMMARY = os.path.join(ROOT, "profiles", "k_update_config2_requests.txt"
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def host_cpu_model():
+    """The host CPU's model name from /proc/cpuinfo, or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def kernel_source_digest() -> str:
@@ -141,8 +154,9 @@ def batched_leg(args, dev, stream):
     FP64 abar, bfloat16 values), autotuned wavefronts per instance and step;
     each instance is switched off once it is within 1e-9 of its certified
     optimum.  Then the same batch with FP64 state (still bfloat16 values),
-    and the same instances one by one with the plain FP64 async kernel.  Times are kernel times between HIP events; the objective checks
-    between them are not counted."""
+    and the same instances one by one with the plain FP64 async kernel.
+    Times are kernel times between HIP events; the objective checks between
+    them (after every epoch, in all three) are not counted."""
     import numpy as np
     import torch
 
@@ -458,12 +472,25 @@ def main():
     if not args.skip_cpu:
         import oracle
         sv = oracle.SparseSaga(p, seed=0)
-        t = time.perf_counter()
-        sv.epochs(args.cpu_epochs)
-        dt = time.perf_counter() - t
+        # one thread pinned to one host core (the GPU work is done by now)
+        prev, core = None, None
+        try:
+            prev = os.sched_getaffinity(0)
+            core = min(prev)
+            os.sched_setaffinity(0, {core})
+        except (AttributeError, OSError):
+            prev = None
+        try:
+            t = time.perf_counter()
+            sv.epochs(args.cpu_epochs)
+            dt = time.perf_counter() - t
+        finally:
+            if prev is not None:
+                os.sched_setaffinity(0, prev)
         cpu = {"value": args.cpu_epochs * p.n / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
                "sample": f"{args.cpu_epochs} epochs ({args.cpu_epochs * p.n} updates) of the same workload, "
-                         f"serial FP64 Sparse SAGA, one thread, {dt:.1f} s; host has {os.cpu_count()} cpus"}
+                         f"serial FP64 Sparse SAGA, one thread, {dt:.1f} s; host has {os.cpu_count()} cpus",
+               "pinned_core": core, "host_cpu": host_cpu_model()}
         log(f"cpu oracle: {cpu}")
 
     out = {
