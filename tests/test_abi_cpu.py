@@ -179,8 +179,8 @@ def test_header_compiles_as_plain_c(tmp_path):
     # the public header and a caller of it are plain C99 (no C++ or HIP types),
     # and such a caller links against the library with the system C toolchain
     pkg = os.path.join(ROOT, "paper_1606_04809_amd")
-    obj, exe = tmp_path / "driver.o", tmp_path / "driver"
+    obj, exe = tmp_path / "caller.o", tmp_path / "caller"
     subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
-                           "-c", os.path.join(ROOT, "tests", "abi_driver.c"), "-o", str(obj)])
+                           "-c", os.path.join(ROOT, "tests", "abi_caller.c"), "-o", str(obj)])
     subprocess.check_call(["gcc", str(obj), "-o", str(exe), "-L", pkg, "-lasaga", "-Wl,-rpath," + pkg])
     assert exe.exists()

@@ -297,7 +297,7 @@ def test_theorem1_envelope():
 
 
 # ---------------------------------------------------------------------------
-# T8: the f* values the GPU is judged against
+# T8: the f* values the GPU results are compared with
 # ---------------------------------------------------------------------------
 
 def test_config1_newton_and_oracle_agree():
