@@ -232,7 +232,8 @@ typedef struct asaga_tune_report {
     int32_t hot_columns;
     int32_t hot_tier_columns;
     double gamma;             /* chosen step                                        */
-    double ms_per_epoch;      /* measured kernel time per epoch at the choice       */
+    double ms_per_epoch;      /* measured kernel time per epoch at the choice
+                                 (batches: one epoch of every active instance)    */
     double est_epochs;        /* estimated epochs from a cold start to the target   */
     double est_seconds;       /* estimated kernel seconds to the target             */
     double step_groups;       /* batches: the step law gamma_k = rule_k * min(step_cap,

@@ -1368,6 +1368,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         double shape_best = INFINITY;
         bool stable = false;
         int misses = 0;
+        Best hb;  // this hot-set size's best law
         for (double sc : scales) {
             ++tried;
             c->step_groups = sc * top;
@@ -1394,7 +1395,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             misses = 0;
             stable = true;
             const double est_s = est_e * (double)ms * 1e-3;
-            if (est_s < best.est_s) best = Best{est_s, est_e, (double)ms, sc * top, S};
+            if (est_s < hb.est_s) hb = Best{est_s, est_e, (double)ms, sc * top, S};
             // FP32 x reaches its rounding floor within a short probe whatever
             // the step, so the rates cannot rank the steps: the largest stable
             // one is kept (in the step-limited regime it converges fastest)
@@ -1402,6 +1403,28 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             shape_best = est_s;
         }
         if (rc) break;
+        if (!std::isfinite(hb.est_s)) continue;
+        // The hot-set sizes are ranked by one epoch of the whole batch under
+        // their law: the calibration instance alone on its few workgroups
+        // hardly feels the hot set's size, the batch (most of the time, every
+        // instance on one or two workgroups) does.
+        set_active(false);
+        c->step_groups = hb.groups;
+        float ms_all = 0.0f;
+        if ((rc = reset_state(c))) break;
+        hipError_t he = hipEventRecord(e0, c->st);
+        if (he == hipSuccess && (rc = batched_piece(c, 1))) break;
+        if (he == hipSuccess) he = hipEventRecord(e1, c->st);
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms_all, e0, e1);
+        if (he != hipSuccess) {
+            rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
+            break;
+        }
+        set_active(true);
+        hb.ms = (double)ms_all;
+        hb.est_s = hb.est_e * hb.ms * 1e-3;
+        if (hb.est_s < best.est_s) best = hb;
     }
     // The short probes see mostly the fast early decrease, which a step at
     // the edge of stability can still show (or not, from one run to the
