@@ -51,6 +51,8 @@ _SIGS = {
     "oracle_step_size": (_D, [_D, _D, _I64, _P]),
     "oracle_saga_indices": (_I, [_I64, _P, _P, _P, _P, _I, _D, _P, _D, _P, _I64, _P, _P, _P]),
     "oracle_saga_run": (_I, [_I64, _P, _P, _P, _P, _I, _D, _P, _D, _U64, _U64, _I64, _P, _P, _P]),
+    "oracle_delayed_saga_run": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P, _D, _U64, _U64, _I64, _I64, _D, _U64,
+                                     _P, _P, _P]),
     "oracle_objective": (_D, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P]),
     "oracle_gradient": (_I, [_I64, _I64, _P, _P, _P, _P, _I, _D, _P, _P]),
     "oracle_memory_average": (_I, [_I64, _I64, _P, _P, _P, _P, _P]),
@@ -232,6 +234,32 @@ class DenseSaga(SparseSaga):
                                             _p(s.alpha), _p(s.abar))
         if rc != 0:
             raise RuntimeError(f"oracle_dense_saga_run failed ({rc})")
+        s.t += int(updates)
+        return s
+
+
+class DelayedSparseSaga(SparseSaga):
+    """Sparse SAGA with simulated inconsistent reads (Section 3.3, bounded
+    overlap tau and Eq. async): each read lacks, independently with
+    probability ``miss``, each coordinate write of each of the last ``tau``
+    updates (decided by a SplitMix64 stream from ``delay_seed``); the writes
+    are additions to the shared state in update order.  ``miss`` = 0 is
+    Sparse SAGA exactly, ``miss`` = 1 reads the state of tau updates earlier.
+    The window of missing writes starts empty at each call of ``run``."""
+
+    def __init__(self, prob, tau: int, miss: float, delay_seed: int = 0x5EED, step: float | None = None,
+                 seed: int = 0, lib=None):
+        super().__init__(prob, step=step, seed=seed, lib=lib)
+        self.tau, self.miss, self.delay_seed = int(tau), float(miss), int(delay_seed)
+
+    def run(self, updates: int, state: State | None = None) -> State:
+        s = self.state if state is None else state
+        rc = self.lib.oracle_delayed_saga_run(self.n, self.d, _p(self.rowptr), _p(self.colidx), _p(self.val),
+                                              _p(self.b), self.loss, self.lam, _p(self.D), self.gamma, self.seed,
+                                              s.t, int(updates), self.tau, self.miss, self.delay_seed,
+                                              _p(s.x), _p(s.alpha), _p(s.abar))
+        if rc != 0:
+            raise RuntimeError(f"oracle_delayed_saga_run failed ({rc})")
         s.t += int(updates)
         return s
 

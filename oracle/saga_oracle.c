@@ -170,6 +170,116 @@ int oracle_saga_run(int64_t n, const int64_t* rowptr, const int32_t* colidx, con
 }
 
 /* ------------------------------------------------------------------ */
+/* Simulated asynchrony: inconsistent reads with bounded overlap        */
+/* ------------------------------------------------------------------ */
+
+/* The asynchronous iteration as the analysis models it (Section 3.3: the
+ * bounded-overlap assumption and Eq. async).  Update t reads
+ *     x^_t = x_t + gamma sum_{u=(t-tau)+}^{t-1} G_u^t g_u ,
+ * the current iterate lacking some coordinate writes of the last tau
+ * updates (G_u^t diagonal with entries in {0, 1}); the reads of abar and of
+ * the memory alpha_i lack the same updates' writes.  The update is computed
+ * from those reads and added to the shared state (atomic additions,
+ * Property 3), in update order, so abar = (1/n) sum_i alpha_i a_i holds
+ * whatever was missing from the reads.
+ * Readings (not fixed by the paper): coordinate v of update u is missing
+ * from read t independently with probability q, decided by SplitMix64
+ * started from delay_seed at counter ((t (tau + 1) + (t - u)) (d + 1) + v),
+ * t and u absolute update counters, v = d standing for the memory write
+ * alpha_{i_u}.  q = 0 is Sparse SAGA exactly; q = 1 makes every read the
+ * state of tau updates earlier.  The window starts empty at each call.
+ * Samples come from the serial stream. */
+static int delay_missing(uint64_t delay_seed, uint64_t t, uint64_t back, int64_t tau, int64_t d, int64_t v,
+                         double q) {
+    if (q <= 0.0) return 0;
+    if (q >= 1.0) return 1;
+    uint64_t key = ((t * (uint64_t)(tau + 1) + back) * (uint64_t)(d + 1)) + (uint64_t)v;
+    double r = (double)(oracle_splitmix64(delay_seed, key) >> 11) * 0x1.0p-53;
+    return r < q;
+}
+
+int oracle_delayed_saga_run(int64_t n, int64_t d, const int64_t* rowptr, const int32_t* colidx, const double* val,
+                            const double* b, int loss, double lambda, const double* D, double gamma,
+                            uint64_t seed, uint64_t t0, int64_t count, int64_t tau, double q, uint64_t delay_seed,
+                            double* x, double* alpha, double* abar) {
+    if (tau < 0 || count < 0) return -1;
+    int64_t maxlen = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (rowptr[i + 1] - rowptr[i] > maxlen) maxlen = rowptr[i + 1] - rowptr[i];
+    int64_t slots = tau > 0 ? tau : 1;
+    int64_t* ring_i = calloc((size_t)slots, sizeof(int64_t));
+    double* ring_dx = calloc((size_t)(slots * (maxlen > 0 ? maxlen : 1)), sizeof(double));
+    double* ring_dab = calloc((size_t)(slots * (maxlen > 0 ? maxlen : 1)), sizeof(double));
+    double* ring_da = calloc((size_t)slots, sizeof(double));
+    double* miss_x = calloc((size_t)(d > 0 ? d : 1), sizeof(double));
+    double* miss_ab = calloc((size_t)(d > 0 ? d : 1), sizeof(double));
+    double* xh = calloc((size_t)(maxlen > 0 ? maxlen : 1), sizeof(double));
+    double* abh = calloc((size_t)(maxlen > 0 ? maxlen : 1), sizeof(double));
+    int rc = 0;
+    if (!ring_i || !ring_dx || !ring_dab || !ring_da || !miss_x || !miss_ab || !xh || !abh) rc = -2;
+    for (int64_t s = 0; s < count && rc == 0; ++s) {
+        uint64_t t = t0 + (uint64_t)s;
+        int64_t i = oracle_sample(seed, t, n);
+        int64_t first = s - tau > 0 ? s - tau : 0;
+        /* the writes of the window's updates that read t does not see */
+        double miss_alpha = 0.0;
+        for (int64_t u = first; u < s; ++u) {
+            int64_t slot = u % slots, iu = ring_i[slot];
+            uint64_t back = (uint64_t)(s - u);
+            for (int64_t k = rowptr[iu]; k < rowptr[iu + 1]; ++k) {
+                int32_t v = colidx[k];
+                if (delay_missing(delay_seed, t, back, tau, d, v, q)) {
+                    miss_x[v] += ring_dx[slot * maxlen + (k - rowptr[iu])];
+                    miss_ab[v] += ring_dab[slot * maxlen + (k - rowptr[iu])];
+                }
+            }
+            if (iu == i && delay_missing(delay_seed, t, back, tau, d, d, q)) miss_alpha += ring_da[slot];
+        }
+        /* inconsistent read of x, abar on S_i and of alpha_i */
+        int64_t rs = rowptr[i], re = rowptr[i + 1];
+        double z = 0.0;
+        for (int64_t k = rs; k < re; ++k) {
+            int32_t v = colidx[k];
+            xh[k - rs] = x[v] - miss_x[v];
+            abh[k - rs] = abar[v] - miss_ab[v];
+            z += val[k] * xh[k - rs];
+        }
+        double delta = oracle_dphi(z, b[i], loss) - (alpha[i] - miss_alpha);
+        /* clear the scratch for the next read */
+        for (int64_t u = first; u < s; ++u) {
+            int64_t iu = ring_i[u % slots];
+            for (int64_t k = rowptr[iu]; k < rowptr[iu + 1]; ++k) {
+                miss_x[colidx[k]] = 0.0;
+                miss_ab[colidx[k]] = 0.0;
+            }
+        }
+        /* the update, added to the shared state and kept for later reads */
+        int64_t slot = tau > 0 ? s % slots : 0;
+        for (int64_t k = rs; k < re; ++k) {
+            int32_t v = colidx[k];
+            double wx = -gamma * (delta * val[k] + D[v] * (abh[k - rs] + lambda * xh[k - rs]));
+            double wab = delta * val[k] / (double)n;
+            x[v] += wx;
+            abar[v] += wab;
+            ring_dx[slot * maxlen + (k - rs)] = wx;
+            ring_dab[slot * maxlen + (k - rs)] = wab;
+        }
+        alpha[i] += delta;
+        ring_i[slot] = i;
+        ring_da[slot] = delta;
+    }
+    free(ring_i);
+    free(ring_dx);
+    free(ring_dab);
+    free(ring_da);
+    free(miss_x);
+    free(miss_ab);
+    free(xh);
+    free(abh);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Sparse SVRG with randomly timed full gradients (Appendix C)         */
 /* ------------------------------------------------------------------ */
 

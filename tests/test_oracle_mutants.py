@@ -217,3 +217,44 @@ def test_dense_lagged_mutant_is_caught(tmp_path, name):
     old, new = DENSE_LAGGED_MUTANTS[name]
     with np.errstate(all="ignore"):
         assert not dense_lagged_pins_pass(build_mutant(tmp_path, name, old, new)), name
+
+
+DELAYED_MUTANTS = {
+    "delayed read adds the missing writes": ("xh[k - rs] = x[v] - miss_x[v];", "xh[k - rs] = x[v] + miss_x[v];"),
+    "delayed window one update short": ("int64_t first = s - tau > 0 ? s - tau : 0;",
+                                        "int64_t first = s - tau + 1 > 0 ? s - tau + 1 : 0;"),
+    "delayed memory read current": ("(alpha[i] - miss_alpha)", "(alpha[i])"),
+    "delayed abar read current": ("abh[k - rs] = abar[v] - miss_ab[v];", "abh[k - rs] = abar[v];"),
+    "delayed scratch not cleared": ("                miss_x[colidx[k]] = 0.0;\n", ""),
+    "delayed write uses the current x": ("D[v] * (abh[k - rs] + lambda * xh[k - rs])",
+                                         "D[v] * (abh[k - rs] + lambda * x[v])"),
+}
+
+
+def delayed_pins_pass(lib) -> bool:
+    from test_oracle_pins import delayed_full_miss_brute_force
+    try:
+        rng = np.random.default_rng(31)
+        for loss in (oracle.LOGISTIC, oracle.SQUARED):
+            p = random_sparse(rng, 20, 9, 0.4, loss, 0.05)
+            for tau in (1, 3, 11):
+                sv = oracle.DelayedSparseSaga(p, tau=tau, miss=1.0, seed=2, lib=lib)
+                sv.run(240)
+                x, alpha, abar = delayed_full_miss_brute_force(p, sv, 240, tau)
+                if not (rel_err(sv.state.x, x) < 1e-12 and rel_err(sv.state.alpha, alpha) < 1e-12
+                        and rel_err(sv.state.abar, abar) < 1e-12):
+                    return False
+        return True
+    except (RuntimeError, FloatingPointError):
+        return False
+
+
+def test_delayed_pins_pass_on_the_oracle():
+    assert delayed_pins_pass(oracle.load())
+
+
+@pytest.mark.parametrize("name", sorted(DELAYED_MUTANTS))
+def test_delayed_mutant_is_caught(tmp_path, name):
+    old, new = DELAYED_MUTANTS[name]
+    with np.errstate(all="ignore"):
+        assert not delayed_pins_pass(build_mutant(tmp_path, name, old, new)), name

@@ -487,3 +487,92 @@ def test_lagged_saga_has_the_dense_iterates(loss):
         assert rel_err(lag.state.x, dense.state.x) < 1e-12
         assert rel_err(lag.state.abar, dense.state.abar) < 1e-13
         assert rel_err(lag.state.alpha, dense.state.alpha) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# T12: simulated asynchrony (Section 3.3: bounded overlap tau, Eq. async)
+# ---------------------------------------------------------------------------
+
+def delayed_full_miss_brute_force(p, sv, updates, tau):
+    """Every write of the last tau updates missing from each read: read s is
+    then the state after max(0, s - tau) updates, taken here from a full
+    history of states (tiny inputs only)."""
+    x, alpha, abar = np.zeros(p.d), np.zeros(p.n), np.zeros(p.d)
+    hist = [(x.copy(), alpha.copy(), abar.copy())]
+    for s, i in enumerate(oracle.sample_stream(sv.seed, 0, updates, p.n)):
+        xr, ar, abr = hist[max(0, s - tau)]
+        lo, hi = p.rowptr[i], p.rowptr[i + 1]
+        cols, vals = p.colidx[lo:hi], p.val[lo:hi]
+        z = 0.0
+        for c, v in zip(cols, vals):
+            z += v * xr[c]
+        delta = oracle.dphi(z, p.b[i], p.loss) - ar[i]
+        for c, v in zip(cols, vals):
+            x[c] += -sv.gamma * (delta * v + sv.D[c] * (abr[c] + p.lam * xr[c]))
+            abar[c] += delta * v / p.n
+        alpha[i] += delta
+        hist.append((x.copy(), alpha.copy(), abar.copy()))
+    return x, alpha, abar
+
+
+@pytest.mark.parametrize("tau", [0, 7, 40])
+def test_delayed_reads_without_misses_are_sparse_saga(tau):
+    p = datagen.config1(n=400, d=120, k=12)
+    a = oracle.SparseSaga(p, seed=4)
+    a.epochs(3)
+    b = oracle.DelayedSparseSaga(p, tau=tau, miss=0.0, seed=4)
+    b.run(3 * p.n)
+    for u, v in ((a.state.x, b.state.x), (a.state.alpha, b.state.alpha), (a.state.abar, b.state.abar)):
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("loss", [oracle.LOGISTIC, oracle.SQUARED])
+def test_delayed_reads_with_every_write_missing_read_the_state_tau_back(loss):
+    rng = np.random.default_rng(31)
+    p = random_sparse(rng, 20, 9, 0.4, loss, 0.05)
+    for tau in (1, 3, 11):
+        sv = oracle.DelayedSparseSaga(p, tau=tau, miss=1.0, seed=2)
+        sv.run(240)
+        x, alpha, abar = delayed_full_miss_brute_force(p, sv, 240, tau)
+        assert rel_err(sv.state.x, x) < 1e-12
+        assert rel_err(sv.state.alpha, alpha) < 1e-12
+        assert rel_err(sv.state.abar, abar) < 1e-12
+
+
+def test_delayed_reads_keep_the_running_average_exact():
+    # the writes are additions of the same delta to alpha_i and (1/n) a_i to
+    # abar, whatever the reads missed
+    rng = np.random.default_rng(32)
+    p = random_sparse(rng, 300, 60, 0.1, oracle.LOGISTIC, 1e-3)
+    sv = oracle.DelayedSparseSaga(p, tau=25, miss=0.5, seed=6)
+    sv.run(5 * p.n)
+    assert rel_err(sv.state.abar, scipy_csr(p).T @ sv.state.alpha / p.n) < 1e-12
+
+
+def test_delayed_reads_are_deterministic_and_follow_their_own_stream():
+    p = datagen.config1(n=400, d=120, k=12)
+    runs = []
+    for ds in (11, 11, 12):
+        sv = oracle.DelayedSparseSaga(p, tau=20, miss=0.5, delay_seed=ds)
+        sv.run(2 * p.n)
+        runs.append(sv.state.x.copy())
+    assert np.array_equal(runs[0], runs[1])
+    assert not np.array_equal(runs[0], runs[2])
+
+
+def test_delayed_reads_small_overlap_converges_large_overlap_needs_a_smaller_step(golden):
+    # Theorem 2: a linear rate for steps below a bound that shrinks with tau
+    p = datagen.config1()
+    fstar = golden["config1"]["f_lower"]
+
+    def rel_after(tau, miss, scale, epochs=30):
+        sv = oracle.DelayedSparseSaga(p, tau=tau, miss=miss)
+        sv.gamma *= scale
+        sv.run(epochs * p.n)
+        return (sv.objective() - fstar) / fstar
+
+    assert rel_after(16, 0.5, 1.0) <= 1e-9
+    assert rel_after(64, 1.0, 1.0) <= 1e-9
+    half = p.n // 2
+    assert rel_after(half, 1.0, 1.0) > 1e-2           # the serial step fails at tau = n/2
+    assert rel_after(half, 1.0, 1.0 / 8) < 1e-3       # an eighth of it converges
