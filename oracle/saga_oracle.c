@@ -23,6 +23,9 @@
  *             abar += (delta/n) a_i,  alpha_i += delta         (Algorithm 2, shared-memory
  *                                                              updates; serial here)
  *
+ *   async     (simulated, oracle_delayed_saga_run) each read lacks some
+ *             coordinate writes of the last tau updates   (Section 3.3, Eq. async)
+ *
  * Readings where the paper is silent (each is listed in the design notes):
  *   - x0 = 0, alpha0 = 0, abar0 = 0 (the Section 2 footnote lets the memory
  *     start at any value; zero is the usual choice).
