@@ -1366,8 +1366,6 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         // instability may grow only near the optimum
         const double top = std::min(groups, kStepGroups);
         double shape_best = INFINITY;
-        bool stable = false;
-        int misses = 0;
         Best hb;  // this hot-set size's best law
         for (double sc : scales) {
             ++tried;
@@ -1388,12 +1386,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
             double est_e = 0.0;
             const bool ok = probe(cps, true, &est_e);
             if (rc) break;
-            if (!ok) {
-                if (stable && ++misses >= 2) break;  // one failure below a pass can be noise
-                continue;
-            }
-            misses = 0;
-            stable = true;
+            if (!ok) continue;  // as for one solve, a failure does not end the ladder
             const double est_s = est_e * (double)ms * 1e-3;
             if (est_s < hb.est_s) hb = Best{est_s, est_e, (double)ms, sc * top, S};
             // FP32 x reaches its rounding floor within a short probe whatever
@@ -1609,22 +1602,18 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         // steps from the largest down, while the estimate improves: past the
         // best stable step, smaller steps only converge more slowly
         double shape_best = INFINITY;
-        int stable = 0, misses = 0;
         for (double sc : scales) {
             ++tried;
             I.gamma = serial_rule * sc;
             double est_e = 0.0;
             const bool ok = probe(cps, &est_e);
             if (rc) break;
-            if (!ok) {
-                // below a step that passed, one failure can be noise (a step at
-                // the edge passes or fails from one run to the next); two end
-                // the ladder
-                if (stable && ++misses >= 2) break;
-                continue;
-            }
-            misses = 0;
-            ++stable;
+            // A failure does not end the ladder: above the stable steps a probe
+            // can pass by chance (4096 wavefronts on the RCV1-shaped matrix:
+            // even the serial rule, estimated at 100-200 epochs, now and then),
+            // and the steps that work lie further down.  The ladder ends once
+            // a passing step estimates worse than the best one of this shape.
+            if (!ok) continue;
             const double est_s = est_e * (double)ms * 1e-3;
             stable_cands.push_back({est_s, est_e, (double)ms, I.gamma, S});
             if (est_s < best.est_s) best = stable_cands.back();
