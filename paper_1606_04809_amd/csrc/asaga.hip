@@ -24,12 +24,14 @@ thread_local std::string g_init_error = "no error";
 constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
 constexpr int kMaxHot = 4096;    // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
 constexpr int kMaxBlock = 1024;  // the update kernels are compiled for at most 1024 threads per workgroup
-// Default workgroup: 512 threads.  1024-thread workgroups share one hot set
-// among twice the samples (fewer flush requests per sample: 400 vs 267 M
-// updates/s on the RCV1-shaped instance at one workgroup per compute unit)
-// but double the samples in flight, which halves the stable step; on
-// instances whose convergence is step-limited (small lambda) that costs
-// more epochs than it saves time, so the larger workgroup is an option.
+// Default workgroup (default_block): 512 threads for one solve, 1024 for a
+// batch.  1024-thread workgroups share one hot set among twice the samples
+// (fewer flush requests per sample: 400 vs 267 M updates/s on the
+// RCV1-shaped instance at one workgroup per compute unit) but double the
+// samples in flight, which halves the stable step; on a single instance
+// whose convergence is step-limited (small lambda) that costs more epochs
+// than it saves time, while an instance of a batch only gets the lane
+// groups its step law uses at the full step.
 // Default asynchronous step: rule * min(1, kStepGroups / G) with G the lane
 // groups (samples) in flight.  The stable step falls like 1/G (Theorem 2);
 // on the RCV1-shaped instance the edge is near 700 / G (2048 in flight:
