@@ -260,15 +260,16 @@ int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_o
  * instance.  With opts.waves = 0 the workgroups the device holds at once
  * are shared equally among the active instances (each at least one, and at
  * most n_k/64 samples in flight), so the instances still running take over
- * the workgroups of those switched off;
- * without opts.step, instance k then steps with
+ * the workgroups of those switched off; without opts.step, instance k then
+ * steps with
  *     gamma_k = rule_k * min(cap, c / G_k),
  * G_k the lane groups (samples in flight) serving it: the stable step
- * shrinks with the delay (Theorem 2).  c and cap come from asaga_autotune;
- * before it, c = 512 (the single-instance default) and cap = 1.  The n_epochs launches are captured once
- * per distinct n_epochs (up to 64; larger counts run in pieces) into a
- * hipGraph on a private stream and replayed on the context's stream (unless
- * opts.plain_launch).  It waits for the previous call's work before
+ * shrinks with the delay (Theorem 2), and an instance gets at most c / cap
+ * lane groups, past which more of them only shrink its step.  c and cap come
+ * from asaga_autotune; before it, c = 512 (the single-instance default) and
+ * cap = 1.  The n_epochs launches are captured once per distinct n_epochs
+ * (up to 64; larger counts run in pieces) into a hipGraph on a private
+ * stream and replayed on the context's stream (unless opts.plain_launch).  It waits for the previous call's work before
  * rewriting the per-instance descriptors and the workgroup map the kernels
  * read. */
 int asaga_epochs(asaga_ctx* ctx, int64_t n_epochs);
@@ -338,31 +339,36 @@ int asaga_widen(asaga_ctx* ctx);
  * gives no estimate, it extrapolates the gradient norm's decay to
  * ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
  * (f is lambda-strongly convex).  Smaller steps are probed while the
- * estimate improves; a count whose probe alone would take longer than the
- * best estimate so far ends the search.  The six best pairs (at most two
- * steps per count) then run 3 * probe_epochs epochs each, and the rate over
- * the last third (closer to the asymptotic rate than the short probe's)
- * decides; a
- * run already certified at a checkpoint counts the epochs to the crossing,
- * interpolated on log ||grad f||^2.  With FP32 x (ASAGA_PREC_MIXED) a
- * gradient norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||)
- * also counts as converged, so that stalling there is not taken for
- * instability.  The best pair is kept, the state is reset to
- * x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair was
- * stable.
- * Batched contexts (opts.step and opts.waves must be 0): the hot-set size (4096 or 1024
- * columns) and the constant c of the step law of asaga_epochs are chosen
- * on the active instance with the smallest lambda (the slowest, the last
- * one running) alone on the device, by the same step ladder (with FP32 x,
- * whose rounding floor is reached within a short probe, the largest stable
- * step); then cap is
- * the largest of 1, 1/2, 1/4, 1/8 with which no active instance is
- * unstable with all of them running, where among many instances unstable
- * means a squared gradient norm that more than doubles between checkpoints
- * or does not decrease from the first to the last (single checkpoints
- * without decrease are noise of the asynchronous updates).
- * `waves` in the report is per instance with all active instances
- * running, `gamma` instance 0's step then. */
+ * estimate improves (a step that fails does not end the search: above the
+ * stable steps a short probe can pass by chance); a count whose probe alone
+ * would take longer than the best estimate so far ends the search.  The six
+ * best pairs (at most two steps per count) then run 3 * probe_epochs epochs
+ * each, and the rate over the last third (closer to the asymptotic rate
+ * than the short probe's) decides; a run already certified at a checkpoint
+ * counts the epochs to the crossing, interpolated on log ||grad f||^2.
+ * With FP32 x (ASAGA_PREC_MIXED) a gradient norm at the floor FP32 rounding
+ * leaves (8 * 2^-24 * L * ||x||) also counts as converged, so that stalling
+ * there is not taken for instability.  The best pair is kept, the state is
+ * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair
+ * was stable.
+ * Batched contexts (opts.step and opts.waves must be 0) get the step law of
+ * asaga_epochs, gamma_k = rule_k * min(cap, c / G_k) with at most c / cap
+ * lane groups per instance, and the hot-set size (4096 or 1024 columns).
+ * c is calibrated on the active instance with the smallest lambda (the
+ * slowest, the last one running) alone on the device, running on c lane
+ * groups at the full step: c from 512 (the single solve's default law) down
+ * the same ladder with the single solve's stability test (with FP32 x, whose
+ * rounding floor is reached within a short probe, the largest stable c),
+ * then the choice again three times longer, down the ladder until one
+ * passes.  The hot-set sizes are ranked by those estimated epochs times one
+ * epoch of every active instance under their law.  cap is then the largest of 1, 1/2,
+ * 1/4, 1/8 with which no active instance is unstable with all of them
+ * running, where among many instances unstable means a squared gradient
+ * norm that more than doubles between checkpoints or does not decrease from
+ * the first to the last (single checkpoints without decrease are noise of
+ * the asynchronous updates).  `waves` in the report is per instance with all
+ * active instances running, `gamma` instance 0's step then, `step_groups`
+ * and `step_cap` the law. */
 int asaga_autotune(asaga_ctx* ctx, double target, int32_t probe_epochs, asaga_tune_report* report);
 
 /* Overlap of the asynchronous updates: an estimate of the delay tau of
