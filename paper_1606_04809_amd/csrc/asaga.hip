@@ -1402,7 +1402,10 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         // The hot-set sizes are ranked by one epoch of the whole batch under
         // their law: the calibration instance alone on its few workgroups
         // hardly feels the hot set's size, the batch (most of the time, every
-        // instance on one or two workgroups) does.
+        // instance on one or two workgroups) does.  Its epochs to the target
+        // are not part of the ranking: at the full step they do not depend on
+        // the hot set, and their estimates vary by some 10% from run to run,
+        // more than the epoch times differ.
         set_active(false);
         c->step_groups = hb.groups;
         float ms_all = 0.0f;
@@ -1419,7 +1422,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         set_active(true);
         hb.ms = (double)ms_all;
         hb.est_s = hb.est_e * hb.ms * 1e-3;
-        if (hb.est_s < best.est_s) best = hb;
+        if (!std::isfinite(best.est_s) || hb.ms < best.ms) best = hb;
     }
     // The short probes see mostly the fast early decrease, which a step at
     // the edge of stability can still show (or not, from one run to the
