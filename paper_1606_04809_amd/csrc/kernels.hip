@@ -33,10 +33,9 @@
 //     of hot columns (those nearly every row touches) is flushed every
 //     round, the rest of the hot set every few rounds, when the untouched
 //     views of the rarest hot columns are reloaded too if the host finds
-//     their lag too long for the step.  Reads of hot columns
-//     touch only LDS; this removes the per-line serialisation of the columns
-//     every row touches, and the tag stalls of reading lines with atomics in
-//     flight.
+//     their lag too long for the step.  Reads of hot columns touch only
+//     LDS; this removes the per-line serialisation of the columns every row
+//     touches, and the tag stalls of reading lines with atomics in flight.
 // The same kernels run the inner steps of sparse SVRG (Appendix C) with the
 // memory frozen (InstArgs::frozen: no abar or alpha writes), and can log a
 // sample of updates' read and completion clocks (InstArgs::tau_log).
