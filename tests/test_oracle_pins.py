@@ -576,3 +576,26 @@ def test_delayed_reads_small_overlap_converges_large_overlap_needs_a_smaller_ste
     half = p.n // 2
     assert rel_after(half, 1.0, 1.0) > 1e-2           # the serial step fails at tau = n/2
     assert rel_after(half, 1.0, 1.0 / 8) < 1e-3       # an eighth of it converges
+
+
+def test_delayed_reads_iterations_do_not_grow_with_small_overlap(golden):
+    # Theorem 2 (and the iteration speedup of Appendix D): below the step
+    # bound, the iterations to a given accuracy do not depend on the overlap;
+    # the bound itself shrinks with tau, so at the serial step a large
+    # overlap costs iterations
+    p = datagen.config1()
+    fstar = golden["config1"]["f_lower"]
+
+    def epochs_to_1e9(tau, scale):
+        sv = oracle.DelayedSparseSaga(p, tau=tau, miss=1.0)
+        sv.gamma *= scale
+        for ep in range(1, 120):
+            sv.run(p.n)
+            if (sv.objective() - fstar) / fstar <= 1e-9:
+                return ep
+        return None
+
+    base = epochs_to_1e9(0, 0.25)
+    for tau in (16, 64):
+        assert abs(epochs_to_1e9(tau, 0.25) - base) <= 1
+    assert epochs_to_1e9(256, 1.0) >= 1.3 * epochs_to_1e9(0, 1.0)
