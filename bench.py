@@ -516,7 +516,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved_gbps / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_update (async, FP64)", "bytes_per_update": bytes_per_update,
-                     "launch_ms": avg_launch_s * 1e3, "memory_side_requests": requests},
+                     "launch_ms": avg_launch_s * 1e3,
+                     # the counters' bytes (beyond L2, some served by the Infinity
+                     # Cache) per second at this run's launch time
+                     "traffic_gbps": traffic / avg_launch_s / 1e9 if traffic else None,
+                     "traffic_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBPS if traffic else None,
+                     "memory_side_requests": requests},
         "time_to_1e-9": tta,
         "time_to_1e-9_autotuned": tta_tuned,
         "time_to_1e-9_svrg": tta_svrg,
