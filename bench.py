@@ -424,10 +424,18 @@ def main():
         prof_shape = None
     traffic = traffic_from_profile(p.n, prof_shape)
     requests = requests_from_profile(p.n, prof_shape)
+    # the device's memory-side request ceiling, measured now (random 16-byte
+    # slots of a state of d columns: atomics only, and one coherent read plus
+    # one atomic, the update's mix)
+    ceil_atomic, ceil_mixed = A.asaga_request_ceiling(p.d)
+    ceiling = {"atomic_per_s": ceil_atomic, "read_plus_atomic_per_s": ceil_mixed}
+    log(f"memory-side request ceiling: {ceil_mixed:.3e}/s (atomics only: {ceil_atomic:.3e}/s)")
     if requests is not None:
         # memory-side requests per second at this run's measured update rate
+        total = (requests["atomic_per_update"] + requests["read_per_update"]) * ups
         requests.update(atomic_per_s=requests["atomic_per_update"] * ups, read_per_s=requests["read_per_update"] * ups,
-                        source=os.path.relpath(REQUEST_SUMMARY, ROOT))
+                        frac_of_ceiling=total / ceil_mixed, source=os.path.relpath(REQUEST_SUMMARY, ROOT))
+        log(f"memory-side requests: {total:.3e}/s = {total / ceil_mixed:.2f} of the ceiling")
 
     # ---- time to 1e-9 relative suboptimality from a cold start ----------------
     def time_to_target(step, shape):
@@ -521,7 +529,7 @@ def main():
                      # Cache) per second at this run's launch time
                      "traffic_gbps": traffic / avg_launch_s / 1e9 if traffic else None,
                      "traffic_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBPS if traffic else None,
-                     "memory_side_requests": requests},
+                     "memory_side_requests": requests, "request_ceiling": ceiling},
         "time_to_1e-9": tta,
         "time_to_1e-9_autotuned": tta_tuned,
         "time_to_1e-9_svrg": tta_svrg,

@@ -418,6 +418,19 @@ int asaga_sync(asaga_ctx* ctx);
  * (for cross-checking the stream; needs a GPU). */
 int asaga_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, int64_t* out_host);
 
+/* The device's memory-side request ceilings, measured now: the bound on the
+ * atomic scatter that Property 3's atomic additions put on the update (the
+ * second roofline of the hot path, next to the HBM stream).  Lane pairs add
+ * to (mode 1: and read, device-coherently) pseudo-random 16-byte (x, abar)
+ * slots of a state of `columns` columns, one memory request per pair and
+ * operation, as the update's cold columns do.  *atomic_per_s: requests per
+ * second with atomic additions only; *mixed_per_s: with one coherent read
+ * and one atomic addition per iteration (the update's mix).  Allocates,
+ * uses and frees a device buffer of 16 * columns bytes on a private stream;
+ * takes tens of milliseconds.  ASAGA_E_ARG for columns outside
+ * [1, 2^27 - 1] or NULL outputs, ASAGA_E_OOM, ASAGA_E_HIP. */
+int asaga_request_ceiling(int64_t columns, double* atomic_per_s, double* mixed_per_s);
+
 /* Message of the last failure of ctx (or of the last failed asaga_init* when
  * ctx is NULL).  Never NULL; the pointer is valid until the next call. */
 const char* asaga_last_error(const asaga_ctx* ctx);

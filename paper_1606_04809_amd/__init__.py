@@ -129,6 +129,8 @@ _SIGS = {
     "asaga_info_get": (ctypes.c_int, [_CTX, ctypes.POINTER(asaga_info)]),
     "asaga_sync": (ctypes.c_int, [_CTX]),
     "asaga_sample_stream": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
+    "asaga_request_ceiling": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]),
     "asaga_last_error": (ctypes.c_char_p, [_CTX]),
     "asaga_free": (None, [_CTX]),
 }
@@ -270,6 +272,14 @@ def asaga_info_get(ctx) -> asaga_info:
 
 def asaga_sync(ctx):
     return _check(_lib.asaga_sync(ctx), ctx)
+
+
+def asaga_request_ceiling(columns: int) -> tuple[float, float]:
+    """(atomic-only, read + atomic) memory-side requests per second of the
+    device, measured over a state of `columns` columns."""
+    a, m = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(_lib.asaga_request_ceiling(int(columns), ctypes.byref(a), ctypes.byref(m)))
+    return a.value, m.value
 
 
 def asaga_sample_stream(seed: int, t0: int, count: int, n: int) -> np.ndarray:

@@ -1839,6 +1839,43 @@ int asaga_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, in
     return ASAGA_OK;
 }
 
+int asaga_request_ceiling(int64_t columns, double* atomic_per_s, double* mixed_per_s) {
+    if (columns < 1 || columns > kMaxD || !atomic_per_s || !mixed_per_s)
+        return fail(nullptr, ASAGA_E_ARG, "bad request ceiling arguments");
+    double* xa = nullptr;
+    hipError_t e = hipMalloc(&xa, (size_t)(2 * columns + 1) * sizeof(double));
+    if (e != hipSuccess) return fail(nullptr, ASAGA_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch_fill_f64(xa, 0.0, 2 * columns + 1, 1, st);
+    // 4096 workgroups of 256 threads (2^19 lane pairs), 256 operations each
+    const int blocks = 4096, iters = 256;
+    double rate[2] = {0.0, 0.0};
+    for (int mode = 0; mode < 2 && e == hipSuccess; ++mode) {
+        e = launch_request_probe(xa, columns, blocks, 8, mode, xa + 2 * columns, st);  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = launch_request_probe(xa, columns, blocks, iters, mode, xa + 2 * columns, st);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double pairs = (double)blocks * 256.0 / 2.0;
+        if (e == hipSuccess) rate[mode] = pairs * iters * (mode == 0 ? 1.0 : 2.0) / ((double)ms * 1e-3);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamSynchronize(st);
+    if (st) (void)hipStreamDestroy(st);
+    (void)hipFree(xa);
+    if (e != hipSuccess) return fail(nullptr, ASAGA_E_HIP, std::string("request ceiling: ") + hipGetErrorString(e));
+    *atomic_per_s = rate[0];
+    *mixed_per_s = rate[1];
+    return ASAGA_OK;
+}
+
 const char* asaga_last_error(const asaga_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 void asaga_free(asaga_ctx* c) {

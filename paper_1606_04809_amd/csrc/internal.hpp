@@ -149,6 +149,11 @@ hipError_t launch_widen_x_slots(double* xa, int64_t d, hipStream_t st);
 hipError_t launch_narrow_f64(const double* in, int64_t count, float* out, hipStream_t st);
 
 hipError_t launch_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, int64_t* out, hipStream_t st);
+// memory-side request probe: blocks x 256 threads, iters operations per lane
+// pair into xa[2 * cols]; mode 0 atomics only, mode 1 one coherent read and
+// one atomic per iteration
+hipError_t launch_request_probe(double* xa, int64_t cols, int blocks, int iters, int mode, double* sink,
+                                hipStream_t st);
 
 int device_cu_count();
 

@@ -1023,6 +1023,33 @@ hipError_t launch_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64
     return hipGetLastError();
 }
 
+// Memory-side request ceiling (a diagnostic of the atomic-rate bound): every
+// lane pair touches a pseudo-random 16-byte (x, abar) slot of a state of
+// `cols` columns per operation, one memory request per pair, as the update
+// kernel's cold columns do.  mode 0: one FP64 atomic addition per iteration;
+// mode 1: one device-coherent read and one atomic addition (to another
+// slot).  The reads feed a value that is stored only if it takes an
+// impossible value, so that they are kept.
+__global__ void k_request_probe(double* xa, int64_t cols, int iters, int mode, double* sink) {
+    const uint64_t pair = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
+    const int comp = threadIdx.x & 1;
+    double acc = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const uint64_t h = splitmix64(0x5EEDull, pair * (uint64_t)iters + (uint64_t)it);
+        const int64_t c1 = (int64_t)(h % (uint64_t)cols);
+        const int64_t c2 = (int64_t)((h >> 32) % (uint64_t)cols);
+        if (mode == 1) acc += __hip_atomic_load(xa + 2 * c1 + comp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(xa + 2 * c2 + comp, 1e-300, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (acc == -1.0) sink[0] = acc;
+}
+
+hipError_t launch_request_probe(double* xa, int64_t cols, int blocks, int iters, int mode, double* sink,
+                                hipStream_t st) {
+    k_request_probe<<<blocks, 256, 0, st>>>(xa, cols, iters, mode, sink);
+    return hipGetLastError();
+}
+
 int device_cu_count() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;

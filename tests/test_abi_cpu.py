@@ -184,3 +184,13 @@ def test_header_compiles_as_plain_c(tmp_path):
                            "-c", os.path.join(ROOT, "tests", "abi_caller.c"), "-o", str(obj)])
     subprocess.check_call(["gcc", str(obj), "-o", str(exe), "-L", pkg, "-lasaga", "-Wl,-rpath," + pkg])
     assert exe.exists()
+
+
+def test_request_ceiling_rejects_bad_arguments():
+    # checked before any device call
+    for cols in (0, -5, 1 << 27):
+        with pytest.raises(A.AsagaError) as e:
+            A.asaga_request_ceiling(cols)
+        assert e.value.code == A.ASAGA_E_ARG
+    lib = A._lib
+    assert lib.asaga_request_ceiling(100, None, None) == A.ASAGA_E_ARG

@@ -52,6 +52,14 @@ def compare_serial(p, epochs, seed=0, tol=1e-12, per_epoch=True, **kw):
         return worst
 
 
+def test_request_ceiling_is_measured():
+    # the memory-side request rate of random 16-byte atomics (and of a read
+    # plus an atomic) on a config-2-sized state: tens of billions per second
+    atomic, mixed = A.asaga_request_ceiling(47_000)
+    say(f"request ceiling: atomics {atomic:.3e}/s, read + atomic {mixed:.3e}/s")
+    assert 1e9 < atomic < 1e12 and 1e9 < mixed < 1e12
+
+
 def test_single_hip_runtime_in_process():
     A.asaga_sample_stream(0, 0, 16, 10)
     assert len(A.hip_runtimes_loaded()) == 1, A.hip_runtimes_loaded()
