@@ -152,7 +152,7 @@ typedef struct asaga_opts {
     int32_t hot_columns;      /* async: the H most-used columns whose writes each
                                  workgroup combines in LDS before adding them to
                                  the shared state (0 = automatic, -1 = none;
-                                 at most 4096).  Automatic: 4096, less the
+                                 at most 5120).  Automatic: 5120, less the
                                  columns v with gamma lambda D_v W > 0.2 (W the
                                  workgroups serving the instance): a hot
                                  column's LDS view is refreshed only when the
@@ -353,7 +353,7 @@ int asaga_widen(asaga_ctx* ctx);
  * was stable.
  * Batched contexts (opts.step and opts.waves must be 0) get the step law of
  * asaga_epochs, gamma_k = rule_k * min(cap, c / G_k) with at most c / cap
- * lane groups per instance, and the hot-set size (4096 or 1024 columns).
+ * lane groups per instance, and the hot-set size (5120 or 1024 columns).
  * c is calibrated on the active instance with the smallest lambda (the
  * slowest, the last one running) alone on the device, running on c lane
  * groups at the full step: c from 512 (the single solve's default law) down

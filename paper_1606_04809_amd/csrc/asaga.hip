@@ -22,7 +22,10 @@ namespace {
 thread_local std::string g_init_error = "no error";
 
 constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
-constexpr int kMaxHot = 4096;    // 32 bytes of LDS per hot column and workgroup: at most 128 KiB
+// 32 bytes of LDS per hot column and workgroup: at most 160 KiB, all of a CU's
+// LDS (on the RCV1-shaped instance 5120 columns run 6% faster than 4096: 13.6
+// instead of 15 cold columns per row)
+constexpr int kMaxHot = 5120;
 constexpr int kMaxBlock = 1024;  // the update kernels are compiled for at most 1024 threads per workgroup
 // Default workgroup (default_block): 512 threads for one solve, 1024 for a
 // batch.  1024-thread workgroups share one hot set among twice the samples
@@ -209,10 +212,10 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->racy != 0 && o->racy != 1) return fail(nullptr, ASAGA_E_ARG, "racy must be 0 or 1");
     if (o->racy && o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "racy applies to async mode only");
     if (o->hot_columns < -1 || o->hot_columns > kMaxHot)
-        return fail(nullptr, ASAGA_E_ARG, "hot_columns must be -1, 0 or in [1, 4096]");
+        return fail(nullptr, ASAGA_E_ARG, "hot_columns must be -1, 0 or in [1, 5120]");
     if (o->flush_every < 0 || o->flush_every > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "flush_every out of range");
     if (o->hot_tier_columns < -1 || o->hot_tier_columns > kMaxHot)
-        return fail(nullptr, ASAGA_E_ARG, "hot_tier_columns must be -1, 0 or in [1, 4096]");
+        return fail(nullptr, ASAGA_E_ARG, "hot_tier_columns must be -1, 0 or in [1, 5120]");
     if (o->hot_tier_every < 0 || o->hot_tier_every > (1 << 16))
         return fail(nullptr, ASAGA_E_ARG, "hot_tier_every out of range");
     if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
@@ -530,7 +533,7 @@ void pick_shape(asaga_ctx* c) {
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
     int hot = c->o.hot_columns;
-    if (hot == 0) hot = 4096;
+    if (hot == 0) hot = kMaxHot;
     if (hot < 0 || S.racy) hot = 0;
     S.hot = (int)std::min<int64_t>(hot, c->d);
     S.flush = c->o.flush_every > 0 ? c->o.flush_every : 1;
@@ -1345,7 +1348,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
     // 1. the calibration instance alone on the device, per hot-set size
     set_active(true);
     std::vector<int> hots;
-    for (int h : {4096, 1024}) {
+    for (int h : {kMaxHot, 1024}) {
         const int hot = (int)std::min<int64_t>(h, c->d);
         if (std::find(hots.begin(), hots.end(), hot) == hots.end()) hots.push_back(hot);
     }

@@ -98,7 +98,7 @@ def test_bad_arguments_are_rejected():
     expect(E, waves=-1)
     expect(E, step=float("nan"))
     expect(E, loss=5)
-    expect(E, hot_columns=5000)
+    expect(E, hot_columns=5121)
     expect(E, hot_columns=-2)
     expect(E, flush_every=-1)
     expect(E, threads_per_block=100)

@@ -306,7 +306,7 @@ def test_hot_view_reload_with_many_workgroups(golden):
                         step=1.0 / (3.0 * L)) as g:
         info = g.info()
         say(f"lambda 1e-8 instance: hot {info.hot_columns} reloaded from column {info.hot_reload_from}")
-        assert info.hot_columns == 4096 and 0 < info.hot_reload_from < info.hot_columns
+        assert info.hot_columns == 5120 and 0 < info.hot_reload_from < info.hot_columns
         ep, rel = run_to(g, fstar, max_epochs=120, every=3)
         say(f"lambda 1e-8 instance, 128 workgroups, gamma = 1/(3L): {ep} epochs, rel {rel:.2e}")
         assert rel <= 1e-9
@@ -322,7 +322,7 @@ def test_async_config2_benchmarked_shape_reaches_1e9(golden):
     rule = 1.0 / (3.0 * (0.25 * float(np.max(np.add.reduceat(p.val ** 2, p.rowptr[:-1]))) + p.lam))
     with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, waves=4096, threads_per_block=1024, step=rule / 8) as g:
         info = g.info()
-        assert (info.waves, info.threads_per_block, info.hot_columns) == (4096, 1024, 4096)
+        assert (info.waves, info.threads_per_block, info.hot_columns) == (4096, 1024, 5120)
         assert info.hot_reload_from == info.hot_columns
         ep, rel = run_to(g, fstar, max_epochs=60)
         say(f"config2 benchmarked shape: {ep} epochs, rel {rel:.2e}")
