@@ -200,27 +200,32 @@ def batched_leg(args, dev, stream):
         log(f"batched {label} autotune: {tune}")
         active = np.ones(ni, dtype=np.uint8)
         rel = np.full(ni, np.inf)
-        reached_at = np.zeros(ni)
-        kernel_s, epochs, updates, check = 0.0, 0, 0, 1
-        while active.any() and epochs < 600:
+        # samples each instance applied (with automatic waves an instance
+        # holding more workgroups than others applies more per launch)
+        applied = np.zeros(ni, dtype=np.int64)
+        kernel_s, launches, check = 0.0, 0, 1
+        while active.any() and launches < 600:
             e0.record(stream)
             g.epochs(check)
             e1.record(stream)
             torch.cuda.synchronize()
             kernel_s += e0.elapsed_time(e1) / 1e3
-            updates += check * int(np.sum(m[active == 1]))
-            epochs += check
+            launches += check
             for k in np.nonzero(active)[0]:
                 rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
                 if rel[k] <= 1e-9:
                     active[k] = 0
-                    reached_at[k] = epochs
+                    applied[k] = g.get_state(int(k), m=int(m[k]))[3]
             g.set_active(active)
-            log(f"batched {label}: {epochs} epochs, {int(active.sum())} instances still active, "
+            log(f"batched {label}: {launches} launches, {int(active.sum())} instances still active, "
                 f"kernel {kernel_s:.3f} s")
+        for k in np.nonzero(active)[0]:
+            applied[k] = g.get_state(int(k), m=int(m[k]))[3]
         g.close()
-        return {"instances": ni, "reached": int(np.sum(rel <= 1e-9)), "epochs_max": epochs,
-                "epochs_median": float(np.median(reached_at[reached_at > 0])) if np.any(reached_at > 0) else None,
+        epochs = applied / m
+        updates = int(applied.sum())
+        return {"instances": ni, "reached": int(np.sum(rel <= 1e-9)), "launches": launches,
+                "epochs_max": float(epochs.max()), "epochs_median": float(np.median(epochs)),
                 "seconds_to_1e-9_all": kernel_s, "updates": updates, "updates_per_s": updates / kernel_s,
                 "worst_rel_subopt": float(np.max(rel)), "autotune": tune}
 

@@ -253,9 +253,14 @@ int asaga_init(asaga_ctx** out, const asaga_problem* prob, const asaga_opts* opt
 int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_opts* opts,
                        const asaga_batch* batch);
 
-/* Apply n_epochs * n samples (n_k per instance in a batch), continuing the
- * sample stream.  Enqueued on the context's stream; returns without waiting
- * for single-instance contexts.
+/* Apply n_epochs * n samples, continuing the sample stream.  Enqueued on the
+ * context's stream; returns without waiting for single-instance contexts.
+ * A batch makes n_epochs launches; in each, instance k applies n_k samples
+ * with opts.waves set, and with automatic waves max(n_k, W_k P) samples, W_k
+ * its workgroups and P the largest ceil(n_j / W_j): every workgroup stays
+ * busy for the whole launch, so an instance holding more workgroups per
+ * sample than others applies more than one epoch (the sample counter t of
+ * each instance, asaga_get_state, says how many).
  * A batched context runs one persistent kernel per epoch over every active
  * instance.  With opts.waves = 0 the workgroups the device holds at once
  * are shared equally among the active instances (each at least one, and at

@@ -869,6 +869,18 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
         h[k].blocks = blocks[k];
         if (I.active) glg = std::max(glg, I.gamma * I.lambda * groups);
     }
+    // With automatic waves the instances hold unequal numbers of workgroups
+    // (160 instances on 256 workgroups: 96 hold two); one epoch each would
+    // leave the extra workgroups idle for half the launch.  Every workgroup
+    // is kept busy instead: instance k applies max(m_k, blocks_k * P)
+    // samples, P = max_j ceil(m_j / blocks_j) the samples per workgroup of
+    // the instance that sets the launch's length: at least one epoch, more
+    // where it holds more workgroups per sample.
+    if (c->o.waves == 0 && !act.empty()) {
+        int64_t per_block = 0;
+        for (size_t k : act) per_block = std::max(per_block, (c->inst[k].m + blocks[k] - 1) / blocks[k]);
+        for (size_t k : act) h[k].count = (uint64_t)std::max(c->inst[k].m, per_block * blocks[k]);
+    }
     S.tier_every = tier_every_from(c, glg);
     for (size_t k : act) S.hot = stable_hot(c, c->inst[k], S.hot, (double)blocks[k]);
     S.tier = std::min(S.tier, S.hot);
@@ -935,8 +947,8 @@ int batched_piece(asaga_ctx* c, int64_t epochs) {
         if ((rc = epochs_graph(c, epochs, S, n_blocks, &exec))) return rc;
         HIPCHK(c, hipGraphLaunch(exec, c->st));
     }
-    for (auto& I : c->inst)
-        if (I.active) I.t += epochs * I.m;
+    for (size_t k = 0; k < c->inst.size(); ++k)
+        if (c->inst[k].active) c->inst[k].t += epochs * (int64_t)c->plan_h[k].count;
     return ASAGA_OK;
 }
 

@@ -505,6 +505,34 @@ def test_batched_instance_gets_only_the_lane_groups_its_step_law_uses():
         assert info.waves * 64 // info.lanes_per_sample > 512
 
 
+def test_batched_workgroups_all_busy_with_unequal_shares():
+    """More instances than fit evenly on the device's workgroups: some hold
+    two, the rest one.  With automatic waves each launch keeps every
+    workgroup busy, so per launch an instance applies P samples per
+    workgroup it holds (P set by the one-workgroup instances): two sample
+    counts, P and 2P, and the running average stays exact."""
+    p = datagen.config2(n=20_000, d=3000)
+    row_fold = datagen.folds5(p.n, seed=0)
+    ni = 200
+    inst_fold = (np.arange(ni) % 5).astype(np.int32)
+    inst_lam = np.full(ni, 1e-3)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, batch=(row_fold, inst_fold, inst_lam)) as g:
+        g.epochs(1)
+        ts, ms = [], []
+        for k in range(ni):
+            m = int(np.sum(row_fold != inst_fold[k]))
+            x, alpha, abar, t = g.get_state(k, m=m)
+            ts.append(t)
+            ms.append(m)
+            if k < 5:
+                sub = datagen.subproblem(p, np.nonzero(row_fold != inst_fold[k])[0], lam=1e-3)
+                assert rel_err(abar, oracle.SparseSaga(sub).memory_average(alpha)) < 1e-11
+        vals = sorted(set(ts))
+        say(f"unequal shares: sample counts {vals}, {ts.count(vals[-1])} instances at the larger")
+        assert len(vals) == 2 and vals[1] == 2 * vals[0] and vals[0] >= max(ms)
+        assert 0 < ts.count(vals[1]) < ni
+
+
 def small_batch(n=12_000, d=3000, lams=(1e-4, 1e-3), folds=(0, 3)):
     p = datagen.config2(n=n, d=d)
     row_fold = datagen.folds5(p.n, seed=0)
