@@ -215,12 +215,12 @@ def batched_leg(args, dev, stream):
                 rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
                 if rel[k] <= 1e-9:
                     active[k] = 0
-                    applied[k] = g.get_state(int(k), m=int(m[k]))[3]
+                    applied[k] = g.instance(int(k)).t
             g.set_active(active)
             log(f"batched {label}: {launches} launches, {int(active.sum())} instances still active, "
                 f"kernel {kernel_s:.3f} s")
         for k in np.nonzero(active)[0]:
-            applied[k] = g.get_state(int(k), m=int(m[k]))[3]
+            applied[k] = g.instance(int(k)).t
         g.close()
         epochs = applied / m
         updates = int(applied.sum())

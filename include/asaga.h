@@ -20,9 +20,20 @@
  * (0 for an empty column).  x, alpha and abar start at 0.
  *
  * Modes:
- *   ASAGA_MODE_SERIAL  one wavefront applies the updates one after another in
- *                      the order of the seeded sample stream (deterministic;
- *                      the sequential Sparse SAGA of Section 2).
+ *   ASAGA_MODE_SERIAL  one lane group applies the updates one after another
+ *                      in the order of the seeded sample stream
+ *                      (deterministic; the sequential Sparse SAGA of Section
+ *                      2).  It runs the asynchronous kernel's code with a
+ *                      single active lane group: lanes_per_sample,
+ *                      threads_per_block, hot_columns, flush_every and the
+ *                      hot_tier and hot_reload options select the same
+ *                      paths (LDS hot set, tiered flush, view reload,
+ *                      long-row chunks) as in ASAGA_MODE_ASYNC, and the
+ *                      iterates do not depend on them beyond rounding.
+ *                      Defaults: 64 lanes, one 64-thread workgroup, no hot
+ *                      set.  A batch in this mode runs every instance
+ *                      sequentially on one workgroup of its own, all
+ *                      instances concurrently.
  *   ASAGA_MODE_ASYNC   many wavefronts apply updates concurrently, lock-free,
  *                      with inconsistent reads and atomic additions (the
  *                      ASAGA implementation of Algorithm 2; atomicity as in
@@ -96,7 +107,10 @@ extern "C" {
 /* precision of the state */
 #define ASAGA_PREC_F64 0   /* x, alpha, abar in FP64                               */
 #define ASAGA_PREC_MIXED 1 /* x, alpha in FP32 (phi' rounded to FP32 before delta
-                              is formed); abar and D in FP64                       */
+                              is formed); abar and D in FP64.  abar receives the
+                              change the FP32 memory entry actually takes,
+                              fl32(alpha_i + fl32(delta)) - alpha_i, so that it
+                              stays the average of the stored memory            */
 
 /* method (single-instance contexts) */
 #define ASAGA_METHOD_SAGA 0 /* Sparse SAGA (Eq. SparseSAGA), the memory updated by every step */
@@ -186,6 +200,13 @@ typedef struct asaga_opts {
     int32_t method;           /* ASAGA_METHOD_* (SVRG: single-instance contexts,
                                  not racy)                                        */
     void* stream;             /* hipStream_t */
+    int32_t hot_reload_from;  /* first hot column whose LDS view a workgroup
+                                 reloads from the shared state at every full
+                                 flush when it wrote nothing to it since the
+                                 last one (0 = automatic: see hot_columns;
+                                 serial mode none; -1 = none; c >= 1: columns
+                                 [c, hot_columns))                              */
+    int32_t reserved;         /* must be 0 */
 } asaga_opts;
 
 /* Many solves over one shared matrix (a regularisation path times
@@ -243,9 +264,17 @@ typedef struct asaga_tune_report {
     double step_cap;
 } asaga_tune_report;
 
-/* Create a context: validate the problem, copy host arrays to the device
- * (device arrays are borrowed), count columns (D, Delta_r), compute L and
- * gamma, zero x, alpha and abar.  On failure *out is NULL and the message is
+/* Create a context for the problem of Section 1 (Eq. finiteSum with the
+ * L2-regularised models of Section 4.1): validate the problem, copy host
+ * arrays to the device (device arrays are borrowed), count each column's
+ * rows to form p_v = #{i : v in S_i}/n and D_v = 1/p_v (Section 2, the
+ * reweighting of Eq. SparseSAGA) and Delta_r = max_v #{i : v in S_i} (the
+ * sparsity measure of Section 3.4), compute L and gamma, and set x, alpha
+ * and abar to 0 (the initial memory of Section 2).
+ * *out: receives the context (owned by the caller, released by asaga_free);
+ * prob, opts: read during the call only.  Errors: ASAGA_E_ARG (NULL or out
+ * of range arguments), ASAGA_E_CSR (malformed problem, see asaga_problem),
+ * ASAGA_E_OOM, ASAGA_E_HIP.  On failure *out is NULL and the message is
  * available from asaga_last_error(NULL). */
 int asaga_init(asaga_ctx** out, const asaga_problem* prob, const asaga_opts* opts);
 
@@ -296,12 +325,39 @@ int asaga_updates(asaga_ctx* ctx, int64_t count);
  * Returns ASAGA_E_DIVERGED if the value is not finite. */
 int asaga_objective(asaga_ctx* ctx, int32_t inst, const double* x_host, double* f_out);
 
-/* grad f(x) = (1/n) sum_i phi'(a_i . x; b_i) a_i + lambda x in FP64 into
- * g_host (double[d]).  x_host as for asaga_objective. */
+/* The gradient of the finite sum (Section 1, Eq. finiteSum, with the
+ * L2-regularised models of Section 4.1):
+ *     grad f(x) = (1/n) sum_i phi'(a_i . x; b_i) a_i + lambda x
+ * in FP64 (per-coordinate sums over the rows) into g_host (double[d],
+ * caller-owned, in the caller's column order).  x_host as for
+ * asaga_objective.  Errors: ASAGA_E_ARG (NULL g_host, inst out of range),
+ * ASAGA_E_HIP. */
 int asaga_full_grad(asaga_ctx* ctx, int32_t inst, const double* x_host, double* g_host);
 
-/* Copy the instance's iterate x (widened to FP64) into x_host (double[d]). */
+/* Copy the instance's iterate x (the x_t of Algorithm 2 after the samples
+ * applied so far, read once every enqueued update has finished; FP32 x
+ * widened to FP64) into x_host (double[d], caller-owned, in the caller's
+ * column order).  Waits for the context's stream.  Errors: ASAGA_E_ARG
+ * (NULL x_host, inst out of range), ASAGA_E_HIP, ASAGA_E_DIVERGED (a
+ * non-finite gradient change appeared during the updates). */
 int asaga_get_x(asaga_ctx* ctx, int32_t inst, double* x_host);
+
+/* What an instance of a context is: its own finite sum of Section 1 over
+ * its m training rows, with its lambda and step. */
+typedef struct asaga_instance {
+    int64_t m;        /* training rows n_k (the length of its alpha)           */
+    int64_t t;        /* samples applied so far                                 */
+    double lambda;
+    double gamma;     /* step size of the next asaga_epochs call (batches: of
+                         the last one)                                          */
+    double L;         /* smoothness constant of the step-size rule              */
+    int32_t fold;     /* held-out fold, -1 for none                             */
+    int32_t active;   /* 1 if it takes part in asaga_epochs                     */
+} asaga_instance;
+
+/* Fill *out for instance `inst` (host memory, caller-owned).  Errors:
+ * ASAGA_E_ARG (NULL context or out, inst out of range). */
+int asaga_instance_get(asaga_ctx* ctx, int32_t inst, asaga_instance* out);
 
 /* Copy / overwrite the instance's whole state: x, abar (double[d]), alpha
  * (double[n_k], in the order of the instance's training rows) and the sample

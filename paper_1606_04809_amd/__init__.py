@@ -74,7 +74,7 @@ class asaga_opts(ctypes.Structure):
                 ("racy", ctypes.c_int32), ("hot_columns", ctypes.c_int32), ("flush_every", ctypes.c_int32),
                 ("threads_per_block", ctypes.c_int32), ("hot_tier_columns", ctypes.c_int32),
                 ("hot_tier_every", ctypes.c_int32), ("plain_launch", ctypes.c_int32), ("method", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("hot_reload_from", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class asaga_batch(ctypes.Structure):
@@ -94,6 +94,11 @@ class asaga_overlap_report(ctypes.Structure):
                 ("tau_p50", ctypes.c_double), ("tau_p99", ctypes.c_double), ("tau_max", ctypes.c_double),
                 ("latency_mean_us", ctypes.c_double), ("latency_p99_us", ctypes.c_double),
                 ("updates_per_s", ctypes.c_double), ("little", ctypes.c_double)]
+
+
+class asaga_instance(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("t", ctypes.c_int64), ("lam", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("L", ctypes.c_double), ("fold", ctypes.c_int32), ("active", ctypes.c_int32)]
 
 
 class asaga_info(ctypes.Structure):
@@ -127,6 +132,7 @@ _SIGS = {
     "asaga_overlap_estimate": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                               ctypes.POINTER(asaga_overlap_report)]),
     "asaga_info_get": (ctypes.c_int, [_CTX, ctypes.POINTER(asaga_info)]),
+    "asaga_instance_get": (ctypes.c_int, [_CTX, ctypes.c_int32, ctypes.POINTER(asaga_instance)]),
     "asaga_sync": (ctypes.c_int, [_CTX]),
     "asaga_sample_stream": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, _P]),
     "asaga_request_ceiling": (ctypes.c_int, [ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
@@ -220,7 +226,8 @@ def asaga_get_x(ctx, inst: int, d: int) -> np.ndarray:
     return x
 
 
-def asaga_get_state(ctx, inst: int, d: int, m: int):
+def asaga_get_state(ctx, inst: int, d: int):
+    m = asaga_instance_get(ctx, inst).m
     x, alpha, abar = np.empty(d), np.empty(m), np.empty(d)
     t = ctypes.c_int64()
     _check(_lib.asaga_get_state(ctx, int(inst), x.ctypes.data, alpha.ctypes.data, abar.ctypes.data, ctypes.byref(t)),
@@ -228,7 +235,8 @@ def asaga_get_state(ctx, inst: int, d: int, m: int):
     return x, alpha, abar, int(t.value)
 
 
-def asaga_set_state(ctx, inst: int, d: int, m: int, x=None, alpha=None, abar=None, t=None):
+def asaga_set_state(ctx, inst: int, d: int, x=None, alpha=None, abar=None, t=None):
+    m = asaga_instance_get(ctx, inst).m
     kx, px = _host_f64(x, d)
     ka, pa = _host_f64(alpha, m)
     kb, pb = _host_f64(abar, d)
@@ -262,6 +270,12 @@ def asaga_overlap_estimate(log, every: int, clock_hz: float, updates_per_s: floa
     _check(_lib.asaga_overlap_estimate(a.ctypes.data, len(a), int(every), float(clock_hz), float(updates_per_s),
                                        ctypes.byref(rep)))
     return rep
+
+
+def asaga_instance_get(ctx, inst: int) -> asaga_instance:
+    out = asaga_instance()
+    _check(_lib.asaga_instance_get(ctx, int(inst), ctypes.byref(out)), ctx)
+    return out
 
 
 def asaga_info_get(ctx) -> asaga_info:
@@ -316,7 +330,7 @@ class Solver:
                  mode=ASAGA_MODE_SERIAL, precision=ASAGA_PREC_F64, step=0.0, seed=0, waves=0,
                  lanes_per_sample=0, racy=0, hot_columns=0, flush_every=0, threads_per_block=0,
                  hot_tier_columns=0, hot_tier_every=0, plain_launch=0, method=ASAGA_METHOD_SAGA, stream=None,
-                 batch=None):
+                 batch=None, hot_reload_from=0):
         self.n, self.d = int(n), int(d)
         arrays = (rowptr, colidx, val, b)
         on_dev = [_is_torch_cuda(a) for a in arrays]
@@ -345,7 +359,8 @@ class Solver:
             stream = stream.cuda_stream
         self.opts = asaga_opts(float(step), int(seed), int(mode), int(precision), int(waves), int(lanes_per_sample),
                                int(racy), int(hot_columns), int(flush_every), int(threads_per_block),
-                               int(hot_tier_columns), int(hot_tier_every), int(plain_launch), int(method), stream)
+                               int(hot_tier_columns), int(hot_tier_every), int(plain_launch), int(method), stream,
+                               int(hot_reload_from), 0)
         if batch is None:
             self.ctx = asaga_init(self.prob, self.opts)
             self.n_inst = 1
@@ -380,11 +395,16 @@ class Solver:
     def get_x(self, inst: int = 0) -> np.ndarray:
         return asaga_get_x(self.ctx, inst, self.d)
 
-    def get_state(self, inst: int = 0, m: int | None = None):
-        return asaga_get_state(self.ctx, inst, self.d, self.n if m is None else m)
+    def get_state(self, inst: int = 0):
+        """(x, alpha, abar, t) of an instance; alpha has the instance's own
+        length (its training rows)."""
+        return asaga_get_state(self.ctx, inst, self.d)
 
-    def set_state(self, inst: int = 0, m: int | None = None, **kw):
-        asaga_set_state(self.ctx, inst, self.d, self.n if m is None else m, **kw)
+    def set_state(self, inst: int = 0, **kw):
+        asaga_set_state(self.ctx, inst, self.d, **kw)
+
+    def instance(self, inst: int = 0) -> asaga_instance:
+        return asaga_instance_get(self.ctx, inst)
 
     def reanchor(self):
         asaga_reanchor(self.ctx)

@@ -224,6 +224,9 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->method != ASAGA_METHOD_SAGA && o->method != ASAGA_METHOD_SVRG)
         return fail(nullptr, ASAGA_E_ARG, "bad method");
     if (o->method == ASAGA_METHOD_SVRG && o->racy) return fail(nullptr, ASAGA_E_ARG, "racy applies to SAGA only");
+    if (o->hot_reload_from < -1 || o->hot_reload_from > kMaxHot)
+        return fail(nullptr, ASAGA_E_ARG, "hot_reload_from must be -1, 0 or in [1, 5120]");
+    if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
     return ASAGA_OK;
 }
 
@@ -450,8 +453,12 @@ int stable_hot(const asaga_ctx* c, const Inst& I, int hot, double workgroups) {
 // request per 4 columns and flush.
 constexpr double kViewLag = 49152.0;
 
-int view_reload_from(const Inst& I, int hot, double workgroups) {
-    if (hot <= 0 || !I.cnt_pmin || !(I.L > 0.0)) return kNoReload;
+int view_reload_from(const asaga_ctx* c, const Inst& I, int hot, double workgroups) {
+    if (hot <= 0) return kNoReload;
+    if (c->o.hot_reload_from > 0) return c->o.hot_reload_from < hot ? c->o.hot_reload_from : kNoReload;
+    // serial mode: the only workgroup's views never lag
+    if (c->o.hot_reload_from < 0 || c->shape.serial) return kNoReload;
+    if (!I.cnt_pmin || !(I.L > 0.0)) return kNoReload;
     const double s = I.gamma * 3.0 * I.L * workgroups;  // (gamma / (1 / 3L)) W
     if (!(s > 0.0)) return kNoReload;
     const double need = (double)I.m * s / kViewLag;  // reload the columns with cnt_v < need
@@ -500,13 +507,17 @@ void pick_shape(asaga_ctx* c) {
     S.racy = c->o.racy != 0;
     S.mixed = c->mixed;
     if (S.serial) {
-        S.lanes = 64;
-        S.waves = 1;
-        S.block = 64;
-        S.hot = 0;
-        S.flush = 1;
-        S.tier = 0;
-        S.tier_every = 1;
+        // one lane group applies the samples in order; the options choose
+        // which of the asynchronous kernel's paths it runs through
+        S.lanes = c->o.lanes_per_sample > 0 ? c->o.lanes_per_sample : 64;
+        S.block = c->o.threads_per_block > 0 ? c->o.threads_per_block : 64;
+        S.block = std::max(S.block, S.lanes);
+        S.waves = S.block / 64;
+        S.hot = c->o.hot_columns > 0 ? (int)std::min<int64_t>(c->o.hot_columns, c->d) : 0;
+        S.flush = c->o.flush_every > 0 ? c->o.flush_every : 1;
+        const int tier = c->o.hot_tier_columns == 0 ? 256 : c->o.hot_tier_columns < 0 ? S.hot : c->o.hot_tier_columns;
+        S.tier = std::min(tier, S.hot);
+        S.tier_every = c->o.hot_tier_every > 0 ? c->o.hot_tier_every : 16;
         return;
     }
     const double mean = (double)c->nnz / (double)c->n;
@@ -579,7 +590,6 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
     if (bt) {
         if (bt->n_inst < 1 || bt->n_inst > 65536 || !bt->inst_fold || !bt->inst_lambda || bt->reserved != 0)
             return fail(nullptr, ASAGA_E_ARG, "bad batch descriptor");
-        if (o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "batched solves run in async mode");
         if (o->racy) return fail(nullptr, ASAGA_E_ARG, "racy is not available for batched solves");
         if (o->method != ASAGA_METHOD_SAGA) return fail(nullptr, ASAGA_E_ARG, "batched solves run Sparse SAGA");
         for (int k = 0; k < bt->n_inst; ++k) {
@@ -831,7 +841,11 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     for (size_t k = 0; k < ni; ++k)
         if (c->inst[k].active) act.push_back(k);
     int n_blocks = 0;
-    if (c->o.waves > 0) {
+    if (S.serial) {
+        // ordered: each active instance on one workgroup of its own
+        for (size_t k : act) blocks[k] = 1;
+        n_blocks = (int)act.size();
+    } else if (c->o.waves > 0) {
         const int bpi = std::max(1, (S.waves + wpb - 1) / wpb);
         n_blocks = (int)ni * bpi;
         for (size_t k = 0; k < ni; ++k) blocks[k] = bpi;
@@ -850,7 +864,7 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     }
     std::vector<BlockMap>& map = c->plan_map;
     map.assign(n_blocks, BlockMap{-1, 0});
-    if (c->o.waves > 0) {
+    if (c->o.waves > 0 && !S.serial) {
         for (int b = 0; b < n_blocks; ++b) map[b] = BlockMap{b / blocks[0], b % blocks[0]};
     } else {
         int b = 0;
@@ -864,7 +878,7 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     for (size_t k = 0; k < ni; ++k) {
         Inst& I = c->inst[k];
         const double groups = (double)blocks[k] * (double)S.block / (double)S.lanes;
-        if (c->o.step <= 0.0 && blocks[k] > 0) I.gamma = I.rule * std::min(c->step_cap, sg / groups);
+        if (c->o.step <= 0.0 && blocks[k] > 0 && !S.serial) I.gamma = I.rule * std::min(c->step_cap, sg / groups);
         h[k] = inst_args(I, (uint64_t)I.t, I.active ? (uint64_t)I.m : 0);
         h[k].blocks = blocks[k];
         if (I.active) glg = std::max(glg, I.gamma * I.lambda * groups);
@@ -876,15 +890,17 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
     // samples, P = max_j ceil(m_j / blocks_j) the samples per workgroup of
     // the instance that sets the launch's length: at least one epoch, more
     // where it holds more workgroups per sample.
-    if (c->o.waves == 0 && !act.empty()) {
+    if (c->o.waves == 0 && !act.empty() && !S.serial) {
         int64_t per_block = 0;
         for (size_t k : act) per_block = std::max(per_block, (c->inst[k].m + blocks[k] - 1) / blocks[k]);
         for (size_t k : act) h[k].count = (uint64_t)std::max(c->inst[k].m, per_block * blocks[k]);
     }
-    S.tier_every = tier_every_from(c, glg);
-    for (size_t k : act) S.hot = stable_hot(c, c->inst[k], S.hot, (double)blocks[k]);
-    S.tier = std::min(S.tier, S.hot);
-    for (size_t k : act) h[k].reload_from = view_reload_from(c->inst[k], S.hot, (double)blocks[k]);
+    if (!S.serial) {
+        S.tier_every = tier_every_from(c, glg);
+        for (size_t k : act) S.hot = stable_hot(c, c->inst[k], S.hot, (double)blocks[k]);
+        S.tier = std::min(S.tier, S.hot);
+    }
+    for (size_t k : act) h[k].reload_from = view_reload_from(c, c->inst[k], S.hot, (double)blocks[k]);
     *Sout = S;
     if ((int64_t)n_blocks > c->map_cap)
         return fail(c, ASAGA_E_STATE, "batched launch needs " + std::to_string(n_blocks) +
@@ -1005,7 +1021,7 @@ int asaga_updates(asaga_ctx* c, int64_t count) {
         }
         InstArgs a = inst_args(I, (uint64_t)I.t, (uint64_t)k);
         a.frozen = c->svrg ? 1 : 0;
-        if (!S.serial) a.reload_from = view_reload_from(I, S.hot, (double)((S.waves * 64 + S.block - 1) / S.block));
+        a.reload_from = view_reload_from(c, I, S.hot, (double)((S.waves * 64 + S.block - 1) / S.block));
         if (c->tau_on) {
             a.tau_log = c->d_tau;
             a.tau_count = c->d_tau_count;
@@ -1798,6 +1814,22 @@ int asaga_overlap(asaga_ctx* c, int64_t n_epochs, asaga_overlap_report* out) {
     return check_flag(c);
 }
 
+int asaga_instance_get(asaga_ctx* c, int32_t inst, asaga_instance* out) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!out) return fail(c, ASAGA_E_ARG, "NULL instance output");
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const Inst& I = c->inst[inst];
+    out->m = I.m;
+    out->t = I.t;
+    out->lambda = I.lambda;
+    out->gamma = I.gamma;
+    out->L = I.L;
+    out->fold = I.fold;
+    out->active = I.active ? 1 : 0;
+    return ASAGA_OK;
+}
+
 int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
     if (!out) return fail(c, ASAGA_E_ARG, "NULL info");
@@ -1824,10 +1856,13 @@ int asaga_info_get(asaga_ctx* c, asaga_info* out) {
     out->hot_tier_columns = c->shape.tier;
     out->hot_tier_every = c->shape.serial ? c->shape.tier_every : tier_every_for(c, c->shape);
     out->hot_reload_from = out->hot_columns;
-    if (!c->shape.serial && !c->d_insts) {
+    if (c->shape.serial && !c->d_insts) {
+        const int rf = view_reload_from(c, I, c->shape.hot, 1.0);
+        if (rf < c->shape.hot) out->hot_reload_from = rf;
+    } else if (!c->d_insts) {
         const double w = (double)((c->shape.waves * 64 + c->shape.block - 1) / c->shape.block);
         const int hot = stable_hot(c, I, c->shape.hot, w);
-        const int rf = view_reload_from(I, hot, w);
+        const int rf = view_reload_from(c, I, hot, w);
         if (rf < hot) out->hot_reload_from = rf;
     } else if (c->d_insts && !c->plan_h.empty() && c->plan_h[0].reload_from < out->hot_columns) {
         out->hot_reload_from = c->plan_h[0].reload_from;

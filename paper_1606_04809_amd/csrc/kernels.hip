@@ -265,14 +265,21 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
 
     // scalar gradient change against the memory
     double g = dphi(z, rr.b, A.loss);
-    if constexpr (MIXED) g = (double)(float)g;  // stored memory is FP32: delta exact in FP64
+    if constexpr (MIXED) g = (double)(float)g;  // stored memory is FP32
     const double al = SERIAL ? load_alpha<MIXED>(I.alpha, rr.j) : rr.alpha;
     const double delta = g - al;
     if (gl == 0 && !isfinite(delta)) *flag = 1;
+    // What the memory entry gains: with FP32 memory the atomic addition
+    // stores fl32(alpha_j + fl32(delta)), which differs from g when |delta|
+    // is far below alpha_j's precision; abar receives that change, not delta,
+    // so that it stays the average of the stored memory (exactly when no
+    // other sample changed alpha_j between this read and the addition).
+    double dmem = delta;
+    if constexpr (MIXED) dmem = (double)((float)al + (float)delta) - al;
 
     // write phase: x_c += -gamma (delta a_c + D_c (abar_c + lambda x_hat_c)) on even lanes,
-    //              abar_c += delta a_c / m on odd lanes
-    const double gam = I.gamma, lam = I.lambda, dm = delta * I.inv_m;
+    //              abar_c += dmem a_c / m on odd lanes
+    const double gam = I.gamma, lam = I.lambda, dm = dmem * I.inv_m;
     // frozen memory: the odd lanes (abar) write nothing
     const bool writes = !(I.frozen && comp == 1);
     if (len <= CAP) {
@@ -363,6 +370,8 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
     const int gl = threadIdx.x & (G - 1);
     const int hot = H.hot;
     const uint64_t kmax = (I.count + slots - 1) / slots;
+    // a group with no sample and no workgroup flush to take part in
+    if (hot == 0 && slot >= I.count) return;
     if (hot > 0) {
         load_view<MIXED>(I.xa, hot);
         __syncthreads();
@@ -413,27 +422,47 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
 // P = 4 passes in registers: rows of up to 2G entries take the fast path.
 constexpr int kPasses = 4;
 
+// Ordered execution (SERIAL): the first lane group of the first workgroup
+// applies every sample of the launch in stream order, reading the memory
+// value alpha_j only after the previous sample's writes and waiting for its
+// own writes before the next sample (an agent-scope fence), which makes the
+// run the sequential Sparse SAGA of Section 2.  The other lane groups apply
+// nothing but take part in the workgroup's flushes of the LDS hot set, so
+// the hot-set combining, the tiered flush, the view refresh and reload, the
+// long-row chunks and every lane-group width run the same code as in the
+// asynchronous launch.
+template <int G, bool SERIAL>
+__device__ __forceinline__ void slot_range(uint64_t rank, uint64_t n_blocks, uint64_t count, uint64_t* slot,
+                                           uint64_t* slots) {
+    if constexpr (SERIAL) {
+        *slots = 1;
+        *slot = rank == 0 && threadIdx.x < G ? 0 : count;  // count: no sample
+    } else {
+        const uint64_t groups = blockDim.x / G;
+        *slot = rank * groups + threadIdx.x / G;
+        *slots = n_blocks * groups;
+    }
+}
+
 template <int G, bool SERIAL, bool RACY, bool MIXED, typename VT>
 __global__ void __launch_bounds__(1024) k_update(MatArgs A, InstArgs I, HotArgs H, int* flag) {
-    const uint64_t groups = blockDim.x / G;
-    const uint64_t slot = blockIdx.x * groups + threadIdx.x / G;
-    const uint64_t slots = (uint64_t)gridDim.x * groups;
+    uint64_t slot, slots;
+    slot_range<G, SERIAL>(blockIdx.x, gridDim.x, I.count, &slot, &slots);
     run_slots<G, kPasses, SERIAL, RACY, MIXED, VT>(A, I, I.t0, slot, slots, H, flag);
 }
 
 // Many instances in one persistent grid: the block map says which instance
 // each workgroup serves and as which of that instance's workgroups.
-template <int G, bool MIXED, typename VT>
+template <int G, bool SERIAL, bool MIXED, typename VT>
 __global__ void __launch_bounds__(1024) k_update_batched(MatArgs A, const InstArgs* insts, const BlockMap* map,
                                                         uint64_t epoch, HotArgs H, int* flag) {
     const BlockMap bm = map[blockIdx.x];
     if (bm.inst < 0) return;
     const InstArgs I = insts[bm.inst];
     if (I.count == 0 || bm.rank >= I.blocks) return;  // instance switched off: its state stays as it is
-    const uint64_t groups = blockDim.x / G;
-    const uint64_t slot = (uint64_t)bm.rank * groups + threadIdx.x / G;
-    const uint64_t slots = (uint64_t)I.blocks * groups;
-    run_slots<G, kPasses, false, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, H, flag);
+    uint64_t slot, slots;
+    slot_range<G, SERIAL>(bm.rank, I.blocks, I.count, &slot, &slots);
+    run_slots<G, kPasses, SERIAL, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, H, flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -451,40 +480,51 @@ static HotArgs hot_args(const UpdateShape& S) {
     return H;
 }
 
+template <int G, bool SERIAL, bool MIXED, typename VT>
+static hipError_t launch_update_g(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int blocks, int* flag,
+                                  hipStream_t st) {
+    const size_t lds = update_lds_bytes(S);
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update<G, SERIAL, false, MIXED, VT>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_update<G, SERIAL, false, MIXED, VT><<<blocks, S.block, lds, st>>>(A, I, hot_args(S), flag);
+    return hipGetLastError();
+}
+
+template <bool SERIAL, bool MIXED, typename VT>
+static hipError_t launch_update_s(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int blocks, int* flag,
+                                  hipStream_t st) {
+    switch (S.lanes) {
+        case 64: return launch_update_g<64, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
+        case 32: return launch_update_g<32, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
+        case 16: return launch_update_g<16, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
+        case 8: return launch_update_g<8, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <bool MIXED, typename VT>
 static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag,
                                    hipStream_t st) {
     if (I.count == 0) return hipSuccess;
-    if (S.serial) {
-        k_update<64, true, false, MIXED, VT><<<1, 64, 0, st>>>(A, I, HotArgs{0, 1, 0, 1}, flag);
-        return hipGetLastError();
-    }
+    // ordered: one workgroup, whose first lane group applies the samples
+    if (S.serial) return launch_update_s<true, MIXED, VT>(A, I, S, 1, flag, st);
     const int threads = S.block;
     const int blocks = (S.waves * 64 + threads - 1) / threads;
-    const size_t lds = update_lds_bytes(S);
-#define ASAGA_LAUNCH(GG)                                                                                     \
-    case GG:                                                                                                 \
-        if (S.racy) {                                                                                        \
-            k_update<GG, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, HotArgs{0, 1, 0, 1}, flag); \
-        } else {                                                                                             \
-            if (lds > 65536) {                                                                               \
-                const hipError_t e = hipFuncSetAttribute(                                                    \
-                    reinterpret_cast<const void*>(&k_update<GG, false, false, MIXED, VT>),                   \
-                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                                   \
-                if (e != hipSuccess) return e;                                                               \
-            }                                                                                                \
-            k_update<GG, false, false, MIXED, VT><<<blocks, threads, lds, st>>>(A, I, hot_args(S), flag);   \
-        }                                                                                                    \
-        break;
-    switch (S.lanes) {
-        ASAGA_LAUNCH(64)
-        ASAGA_LAUNCH(32)
-        ASAGA_LAUNCH(16)
-        ASAGA_LAUNCH(8)
-        default: return hipErrorInvalidValue;
+    if (S.racy) {
+        const HotArgs none{0, 1, 0, 1};
+        switch (S.lanes) {
+            case 64: k_update<64, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 32: k_update<32, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 16: k_update<16, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 8: k_update<8, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
     }
-#undef ASAGA_LAUNCH
-    return hipGetLastError();
+    return launch_update_s<false, MIXED, VT>(A, I, S, blocks, flag, st);
 }
 
 hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag, hipStream_t st) {
@@ -502,23 +542,31 @@ hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape
     return hipErrorInvalidValue;
 }
 
+template <int G, bool SERIAL, bool MIXED, typename VT>
+static hipError_t launch_batched_gs(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
+                                    uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
+    const size_t lds = update_lds_bytes(S);
+    if (lds > 65536) {
+        const hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_batched<G, SERIAL, MIXED, VT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_update_batched<G, SERIAL, MIXED, VT><<<n_blocks, S.block, lds, st>>>(A, insts, map, epoch, hot_args(S), flag);
+    return hipGetLastError();
+}
+
 template <int G, bool MIXED, typename VT>
 static hipError_t launch_batched_g(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
                                    uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
-    const size_t lds = update_lds_bytes(S);
-    if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_batched<G, MIXED, VT>),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
-    k_update_batched<G, MIXED, VT><<<n_blocks, S.block, lds, st>>>(A, insts, map, epoch, hot_args(S), flag);
-    return hipGetLastError();
+    return S.serial ? launch_batched_gs<G, true, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st)
+                    : launch_batched_gs<G, false, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
 }
 
 template <int G, bool MIXED, typename VT>
 static int resident_g(const UpdateShape& S) {
     const size_t lds = update_lds_bytes(S);
-    const void* fn = reinterpret_cast<const void*>(&k_update_batched<G, MIXED, VT>);
+    const void* fn = reinterpret_cast<const void*>(&k_update_batched<G, false, MIXED, VT>);
     if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int per_cu = 0;

@@ -36,7 +36,8 @@ def test_struct_layouts_match_header(tmp_path):
     src = tmp_path / "layout.c"
     checks = []
     for cname, py in (("asaga_problem", A.asaga_problem), ("asaga_opts", A.asaga_opts),
-                      ("asaga_batch", A.asaga_batch), ("asaga_info", A.asaga_info)):
+                      ("asaga_batch", A.asaga_batch), ("asaga_info", A.asaga_info),
+                      ("asaga_instance", A.asaga_instance)):
         checks.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
         for fname, _ in py._fields_:
             cf = {"lam": "lambda"}.get(fname, fname)
@@ -47,7 +48,8 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
     for cname, py in (("asaga_problem", A.asaga_problem), ("asaga_opts", A.asaga_opts),
-                      ("asaga_batch", A.asaga_batch), ("asaga_info", A.asaga_info)):
+                      ("asaga_batch", A.asaga_batch), ("asaga_info", A.asaga_info),
+                      ("asaga_instance", A.asaga_instance)):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
@@ -63,7 +65,7 @@ def expect(code, **changes):
     opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
                                                               "waves", "step", "loss", "hot_columns",
                                                               "flush_every", "threads_per_block",
-                                                              "plain_launch", "method")}
+                                                              "plain_launch", "method", "hot_reload_from")}
     kw.update(changes)
     with pytest.raises(A.AsagaError) as ei:
         A.Solver(**kw, **opts)
@@ -107,6 +109,8 @@ def test_bad_arguments_are_rejected():
     expect(E, plain_launch=2)
     expect(E, method=2)
     expect(E, method=A.ASAGA_METHOD_SVRG, racy=1, mode=A.ASAGA_MODE_ASYNC)   # racy is a SAGA control
+    expect(E, hot_reload_from=-2)
+    expect(E, hot_reload_from=5121)
     expect(E, n=0, rowptr=np.array([0]), colidx=np.array([], np.int32), val=np.array([]), b=np.array([]))
 
 
@@ -165,6 +169,19 @@ def test_overlap_estimator_rejects_bad_input():
         A.asaga_overlap_estimate(np.array([[1, 5]]), every=1, clock_hz=0.0)
     r = A.asaga_overlap_estimate(np.zeros((4, 2), dtype=np.int64), every=1, clock_hz=1.0)
     assert r.logged == 0
+
+
+def test_opts_reserved_must_be_zero():
+    # checked with the other options, before any device call
+    kw = good()
+    rowptr = np.ascontiguousarray(kw["rowptr"], dtype=np.int64)
+    prob = A.asaga_problem(kw["n"], kw["d"], rowptr.ctypes.data, kw["colidx"].ctypes.data, kw["val"].ctypes.data,
+                           kw["b"].ctypes.data, kw["lam"], A.ASAGA_VAL_F64, A.ASAGA_LOSS_LOGISTIC, A.ASAGA_MEM_HOST, 0)
+    opts = A.asaga_opts()
+    opts.reserved = 1
+    with pytest.raises(A.AsagaError) as ei:
+        A.asaga_init(prob, opts)
+    assert ei.value.code == A.ASAGA_E_ARG
 
 
 def test_batched_svrg_is_rejected():

@@ -479,7 +479,7 @@ def test_batched_instances_reach_their_own_optimum():
         for k, (f, lam) in enumerate(zip(inst_fold, inst_lam)):
             rows = np.nonzero(row_fold != f)[0]
             sub = datagen.subproblem(p, rows, lam=lam)
-            x, alpha, abar, t = g.get_state(k, m=len(rows))
+            x, alpha, abar, t = g.get_state(k)
             assert t == 5 * (e + 1) * len(rows)
             assert rel_err(abar, oracle.SparseSaga(sub).memory_average(alpha)) < 1e-11
 
@@ -521,7 +521,7 @@ def test_batched_workgroups_all_busy_with_unequal_shares():
         ts, ms = [], []
         for k in range(ni):
             m = int(np.sum(row_fold != inst_fold[k]))
-            x, alpha, abar, t = g.get_state(k, m=m)
+            x, alpha, abar, t = g.get_state(k)
             ts.append(t)
             ms.append(m)
             if k < 5:
@@ -561,10 +561,10 @@ def test_batched_graph_replays_match_plain_launches():
             fg = [gg.objective(k) for k in range(4)]    # eager work between replays
             fp = [gp.objective(k) for k in range(4)]
             assert fg == fp, (r, fg, fp)
-            new = [gg.get_state(k, m=m[k]) for k in range(4)]
+            new = [gg.get_state(k) for k in range(4)]
             for k in range(4):
                 xg, ag, bg, tg = new[k]
-                xp, ap, bp, tp = gp.get_state(k, m=m[k])
+                xp, ap, bp, tp = gp.get_state(k)
                 assert tg == tp
                 assert np.array_equal(xg, xp) and np.array_equal(ag, ap) and np.array_equal(bg, bp), (r, k)
                 if r >= 3 and k == 1:
