@@ -325,6 +325,31 @@ int asaga_updates(asaga_ctx* ctx, int64_t count);
  * Returns ASAGA_E_DIVERGED if the value is not finite. */
 int asaga_objective(asaga_ctx* ctx, int32_t inst, const double* x_host, double* f_out);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * objective of asaga_objective, for a problem held in device memory, with
+ * no context and no allocation of any kind.
+ *     f(x) = (1/n) sum_i phi(a_i . x; b_i) + (lambda/2) ||x||^2
+ * prob: its arrays in device memory (mem = ASAGA_MEM_DEVICE), in the
+ *   caller's column order, laid out as asaga_problem says and meeting its
+ *   requirements (they are read, not checked: validate them once with
+ *   asaga_init if they come from elsewhere); 1 <= n <= ASAGA_NOALLOC_MAX_ROWS.
+ * x_dev: double[d] in device memory.  f_dev: one double in device memory,
+ *   written by the last kernel (not checked for being finite).
+ * stream: a hipStream_t (NULL = null stream); the work is enqueued there and
+ *   the call returns without waiting.
+ * Scratch: the per-row terms and partial sums go to a static device array
+ * of ASAGA_NOALLOC_MAX_ROWS + 1026 doubles (32 MiB), one copy on each GPU
+ * the library runs on, held until the process ends and located at the
+ * first call on each device.  Every call on a GPU uses that GPU's copy:
+ * calls that overlap on one GPU (other streams, other threads) race and
+ * must be ordered by the caller.  Nothing in it needs clearing.
+ * Errors (nothing enqueued): ASAGA_E_ARG (NULL pointers, mem not DEVICE, n
+ * or d out of range, bad enum, lambda not > 0, reserved not 0), ASAGA_E_HIP;
+ * the message is available from asaga_last_error(NULL). */
+#define ASAGA_NOALLOC_MAX_ROWS 4194304
+int asaga_objective_noalloc(const asaga_problem* prob, const double* x_dev, double* f_dev, void* stream);
+
 /* The gradient of the finite sum (Section 1, Eq. finiteSum, with the
  * L2-regularised models of Section 4.1):
  *     grad f(x) = (1/n) sum_i phi'(a_i . x; b_i) a_i + lambda x

@@ -56,6 +56,7 @@ ASAGA_PREC_F64 = 0
 ASAGA_PREC_MIXED = 1
 ASAGA_METHOD_SAGA = 0
 ASAGA_METHOD_SVRG = 1
+ASAGA_NOALLOC_MAX_ROWS = 4194304
 
 ERROR_NAMES = {0: "ASAGA_OK", -1: "ASAGA_E_ARG", -2: "ASAGA_E_CSR", -3: "ASAGA_E_OOM", -4: "ASAGA_E_HIP",
                -5: "ASAGA_E_DIVERGED", -6: "ASAGA_E_STATE"}
@@ -121,6 +122,7 @@ _SIGS = {
     "asaga_set_active": (ctypes.c_int, [_CTX, _P]),
     "asaga_updates": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "asaga_objective": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
+    "asaga_objective_noalloc": (ctypes.c_int, [ctypes.POINTER(asaga_problem), _P, _P, _P]),
     "asaga_full_grad": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P]),
     "asaga_get_x": (ctypes.c_int, [_CTX, ctypes.c_int32, _P]),
     "asaga_get_state": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
@@ -211,6 +213,15 @@ def asaga_objective(ctx, inst: int, d: int, x=None) -> float:
     f = ctypes.c_double()
     _check(_lib.asaga_objective(ctx, int(inst), px, ctypes.byref(f)), ctx)
     return f.value
+
+
+def asaga_objective_noalloc(prob: asaga_problem, x_dev: int, f_dev: int, stream=None):
+    """Enqueue f(x) of a device-resident problem into the device double at
+    f_dev (x_dev: device double[d]); allocates nothing.  ``stream``: a
+    torch.cuda.Stream or a raw hipStream_t integer (None: null stream)."""
+    if stream is not None and not isinstance(stream, int):
+        stream = stream.cuda_stream
+    return _check(_lib.asaga_objective_noalloc(ctypes.byref(prob), x_dev, f_dev, stream))
 
 
 def asaga_full_grad(ctx, inst: int, d: int, x=None) -> np.ndarray:

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -970,6 +971,41 @@ int batched_piece(asaga_ctx* c, int64_t epochs) {
 
 }  // namespace
 
+// Scratch of asaga_objective_noalloc, one copy per device for the life of
+// the process: the per-row terms phi(a_i . x; b_i) (computed in place over
+// the row dots), then the partial and final sums.  The name is a host-side
+// stand-in in host code: kernels get the device address that
+// hipGetSymbolAddress reports for the current device.
+constexpr int64_t kNoAllocRows = (int64_t)1 << 22;
+constexpr int64_t kNoAllocScratch = kNoAllocRows + kSumParts + 2;
+static __device__ __align__(256) double scratch[kNoAllocScratch];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // by device ordinal; nullptr until first looked up
+
+// Device address of `scratch` on the current device (looked up once per
+// device, with that device current).
+int scratch_on_current_device(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, ASAGA_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, ASAGA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return ASAGA_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int asaga_set_active(asaga_ctx* c, const uint8_t* active) {
@@ -1072,6 +1108,38 @@ int asaga_objective(asaga_ctx* c, int32_t inst, const double* x_host, double* f_
     const double f = s[0] / (double)I.m + 0.5 * I.lambda * s[1];
     *f_out = f;
     if (!std::isfinite(f)) return fail(c, ASAGA_E_DIVERGED, "objective is not finite");
+    return ASAGA_OK;
+}
+
+int asaga_objective_noalloc(const asaga_problem* p, const double* x_dev, double* f_dev, void* stream) {
+    if (!p || !x_dev || !f_dev) return fail(nullptr, ASAGA_E_ARG, "NULL problem, x_dev or f_dev");
+    if (p->mem != ASAGA_MEM_DEVICE) return fail(nullptr, ASAGA_E_ARG, "problem arrays must be in device memory");
+    if (p->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "reserved field must be 0");
+    if (p->n < 1 || p->n > kNoAllocRows)
+        return fail(nullptr, ASAGA_E_ARG,
+                    "n = " + std::to_string(p->n) + " outside [1, " + std::to_string(kNoAllocRows) +
+                        "]: the allocation-free objective holds one term per row in a fixed scratch array");
+    if (p->d < 1 || p->d > kMaxD) return fail(nullptr, ASAGA_E_ARG, "d must be in [1, 2^27 - 1]");
+    if (!p->rowptr || !p->colidx || !p->val || !p->b) return fail(nullptr, ASAGA_E_ARG, "NULL problem array");
+    if (p->val_dtype < ASAGA_VAL_F64 || p->val_dtype > ASAGA_VAL_BF16)
+        return fail(nullptr, ASAGA_E_ARG, "bad val_dtype");
+    if (p->loss != ASAGA_LOSS_LOGISTIC && p->loss != ASAGA_LOSS_SQUARED) return fail(nullptr, ASAGA_E_ARG, "bad loss");
+    if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(nullptr, ASAGA_E_ARG, "lambda must be > 0 and finite");
+    double* sc = nullptr;
+    int rc = scratch_on_current_device(&sc);
+    if (rc) return rc;
+    double* terms = sc;                       // [n]
+    double* part = sc + kNoAllocRows;         // [kSumParts]
+    double* sums = part + kSumParts;          // [2]
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const MatArgs A{p->rowptr, p->colidx, p->val, p->b, p->n, p->d, p->val_dtype, p->loss};
+    const XView x{x_dev, 1, 0};
+    hipError_t e = launch_rowdot(A, nullptr, p->n, x, terms, st);
+    if (e == hipSuccess) e = launch_phi_terms(A, nullptr, p->n, terms, terms, st);
+    if (e == hipSuccess) e = launch_sum(terms, p->n, part, sums + 0, st);
+    if (e == hipSuccess) e = launch_sum_x2(x, p->d, part, sums + 1, st);
+    if (e == hipSuccess) e = launch_objective_finish(sums, (double)p->n, p->lambda, f_dev, st);
+    if (e != hipSuccess) return fail(nullptr, ASAGA_E_HIP, std::string("objective launch: ") + hipGetErrorString(e));
     return ASAGA_OK;
 }
 

@@ -138,6 +138,8 @@ hipError_t launch_axpy_x(XView x, int64_t d, double lambda, double* g, hipStream
 constexpr int kSumParts = 1024;
 hipError_t launch_sum(const double* in, int64_t count, double* part, double* out, hipStream_t st);
 hipError_t launch_sum_x2(XView x, int64_t d, double* part, double* out, hipStream_t st);
+// *f = sums[0] / m + (lambda / 2) sums[1]: the objective from its two sums (one thread)
+hipError_t launch_objective_finish(const double* sums, double m, double lambda, double* f, hipStream_t st);
 // out[v] = x[rank[v]]  (back to the caller's column order)
 hipError_t launch_gather_view(XView x, const int32_t* rank, int64_t d, double* out, hipStream_t st);
 // slot[rank[v] * stride] = in[v]  (into the relabelled order; f32 stores a float in the slot)

@@ -1002,6 +1002,15 @@ hipError_t launch_sum_x2(XView x, int64_t d, double* part, double* out, hipStrea
     return hipGetLastError();
 }
 
+__global__ void k_objective_finish(const double* sums, double m, double lambda, double* f) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *f = sums[0] / m + 0.5 * lambda * sums[1];
+}
+
+hipError_t launch_objective_finish(const double* sums, double m, double lambda, double* f, hipStream_t st) {
+    k_objective_finish<<<1, 64, 0, st>>>(sums, m, lambda, f);
+    return hipGetLastError();
+}
+
 __global__ void k_gather_view(XView x, const int32_t* rank, int64_t d, double* out) {
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < d; v += (int64_t)gridDim.x * blockDim.x)
         out[v] = xget(x, rank[v]);
