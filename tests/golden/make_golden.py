@@ -17,6 +17,13 @@ computed by the CPU oracle only (never by the HIP library).
 
 Each entry records the sha256 digest of the generated instance, so a test
 can check that it regenerated the same problem.
+
+    python tests/golden/make_golden.py tta [config1 ... config5]
+
+adds to each entry the oracle's own epochs (serial step rule, seed 0,
+checked after every epoch) to 1e-9 relative suboptimality against the
+stored f*, with the host seconds they took ("oracle_tta"; per instance for
+config5).
 """
 from __future__ import annotations
 
@@ -96,6 +103,61 @@ def entry_config5(workers):
             "n": _BATCH.problem.n, "d": _BATCH.problem.d, "nnz": _BATCH.problem.nnz, "n_inst": _BATCH.n_inst}
 
 
+def oracle_epochs_to(p, fstar, target=1e-9, max_epochs=3000):
+    """The oracle's own serial Sparse SAGA (serial step rule, seed 0) from
+    x = 0: epochs until (f - f*)/f* <= target, checked after every epoch,
+    and the host seconds its updates took (the checks not counted)."""
+    sv = oracle.SparseSaga(p)
+    secs, ep, rel = 0.0, 0, float("inf")
+    while ep < max_epochs:
+        t = time.perf_counter()
+        sv.epochs(1)
+        secs += time.perf_counter() - t
+        ep += 1
+        rel = (sv.objective() - fstar) / fstar
+        if rel <= target:
+            break
+    return {"target": target, "epochs": ep, "reached": bool(rel <= target), "final_rel": rel,
+            "host_seconds": round(secs, 2), "seconds_per_epoch": secs / ep}
+
+
+def _config5_tta(k):
+    q = _BATCH.instance(k)
+    r = oracle_epochs_to(q, _FSTAR5[k], max_epochs=600)
+    print(f"  instance {k}: {r}", flush=True)
+    return k, r
+
+
+_FSTAR5 = None
+
+
+def add_tta(names, workers):
+    """Adds the oracle's own epochs to 1e-9 ("oracle_tta") to stored entries."""
+    import multiprocessing as mp
+    global _BATCH, _FSTAR5
+    data = json.load(open(OUT))
+    for name in names:
+        t = time.time()
+        if name == "config5":
+            _BATCH = datagen.config5()
+            if data[name]["digest"] != _batch_digest(_BATCH):
+                raise SystemExit("config5 differs from the stored batch")
+            _FSTAR5 = {e["k"]: e["f_lower"] for e in data[name]["instances"]}
+            order = sorted(range(_BATCH.n_inst), key=lambda k: _BATCH.inst_lambda[k])
+            with mp.get_context("fork").Pool(workers) as pool:
+                res = dict(pool.imap_unordered(_config5_tta, order))
+            for e in data[name]["instances"]:
+                e["oracle_tta"] = res[e["k"]]
+        else:
+            p = datagen.by_name(name)
+            if data[name]["digest"] != p.digest():
+                raise SystemExit(f"{name} differs from the stored instance")
+            data[name]["oracle_tta"] = oracle_epochs_to(p, data[name]["f_lower"])
+            print(f"{name}: {data[name]['oracle_tta']}", flush=True)
+        print(f"{name}: oracle epochs to 1e-9 in {time.time() - t:.1f} s", flush=True)
+        json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
+
+
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
@@ -124,4 +186,8 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["config1", "config3", "config2", "config4"])
+    if sys.argv[1:2] == ["tta"]:
+        add_tta(sys.argv[2:] or ["config1", "config3", "config2", "config4", "config5"],
+                int(os.environ.get("GOLDEN_WORKERS", "7")))
+    else:
+        main(sys.argv[1:] or ["config1", "config3", "config2", "config4"])
