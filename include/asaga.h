@@ -111,6 +111,21 @@ extern "C" {
                               change the FP32 memory entry actually takes,
                               fl32(alpha_i + fl32(delta)) - alpha_i, so that it
                               stays the average of the stored memory            */
+#define ASAGA_PREC_F32 2   /* x, alpha and abar in FP32 (phi' rounded as above).
+                              A column's x and abar share 8 bytes, so the two
+                              lanes that add to them issue one memory request
+                              (the mixed layout's FP32 x and FP64 abar take two)
+                              and the LDS hot set holds up to 10240 columns.
+                              The hot columns' FP32 sums are compensated: each
+                              flush's rounding error (known exactly from the
+                              returning atomic) stays pending in the
+                              workgroup and is added with its next flush of
+                              the slot; at most half a unit in the last place
+                              per slot and workgroup is dropped per launch.
+                              abar receives the change the FP32 memory entry
+                              takes, as above.  asaga_reanchor recomputes abar
+                              in FP64 (then rounds it once); asaga_widen
+                              switches to FP64 for the final polish          */
 
 /* method (single-instance contexts) */
 #define ASAGA_METHOD_SAGA 0 /* Sparse SAGA (Eq. SparseSAGA), the memory updated by every step */
@@ -166,7 +181,8 @@ typedef struct asaga_opts {
     int32_t hot_columns;      /* async: the H most-used columns whose writes each
                                  workgroup combines in LDS before adding them to
                                  the shared state (0 = automatic, -1 = none;
-                                 at most 5120).  Automatic: 5120, less the
+                                 at most 5120, or 10240 with ASAGA_PREC_F32).
+                                 Automatic: that maximum, less the
                                  columns v with gamma lambda D_v W > 0.2 (W the
                                  workgroups serving the instance): a hot
                                  column's LDS view is refreshed only when the
@@ -432,7 +448,7 @@ int asaga_widen(asaga_ctx* ctx);
  * each, and the rate over the last third (closer to the asymptotic rate
  * than the short probe's) decides; a run already certified at a checkpoint
  * counts the epochs to the crossing, interpolated on log ||grad f||^2.
- * With FP32 x (ASAGA_PREC_MIXED) a gradient norm at the floor FP32 rounding
+ * With FP32 x (ASAGA_PREC_MIXED, ASAGA_PREC_F32) a gradient norm at the floor FP32 rounding
  * leaves (8 * 2^-24 * L * ||x||) also counts as converged, so that stalling
  * there is not taken for instability.  The best pair is kept, the state is
  * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair

@@ -54,6 +54,7 @@ ASAGA_MODE_SERIAL = 0
 ASAGA_MODE_ASYNC = 1
 ASAGA_PREC_F64 = 0
 ASAGA_PREC_MIXED = 1
+ASAGA_PREC_F32 = 2
 ASAGA_METHOD_SAGA = 0
 ASAGA_METHOD_SVRG = 1
 ASAGA_NOALLOC_MAX_ROWS = 4194304

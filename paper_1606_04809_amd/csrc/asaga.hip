@@ -27,6 +27,8 @@ constexpr int64_t kMaxD = ((int64_t)1 << 27) - 1;
 // LDS (on the RCV1-shaped instance 5120 columns run 6% faster than 4096: 13.6
 // instead of 15 cold columns per row)
 constexpr int kMaxHot = 5120;
+// the FP32 layout keeps 16 bytes per hot column: twice the columns
+constexpr int kMaxHotF32 = 10240;
 constexpr int kMaxBlock = 1024;  // the update kernels are compiled for at most 1024 threads per workgroup
 // Default workgroup (default_block): 512 threads for one solve, 1024 for a
 // batch.  1024-thread workgroups share one hot set among twice the samples
@@ -75,7 +77,8 @@ struct asaga_ctx {
     double* b = nullptr;
     asaga_opts o{};
     hipStream_t st = nullptr;
-    bool mixed = false;
+    bool mixed = false;          // FP32 x and alpha (mixed and FP32 layouts)
+    int layout = kLayF64;        // kLay*: the state layout of ASAGA_PREC_*
     bool svrg = false;           // ASAGA_METHOD_SVRG
     UpdateShape shape{};
     std::vector<Inst> inst;
@@ -203,8 +206,10 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (p->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "problem.reserved must be 0");
     if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(nullptr, ASAGA_E_ARG, "lambda must be > 0 and finite");
     if (o->mode != ASAGA_MODE_SERIAL && o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "bad mode");
-    if (o->precision != ASAGA_PREC_F64 && o->precision != ASAGA_PREC_MIXED)
+    if (o->precision != ASAGA_PREC_F64 && o->precision != ASAGA_PREC_MIXED && o->precision != ASAGA_PREC_F32)
         return fail(nullptr, ASAGA_E_ARG, "bad precision");
+    const int max_hot = o->precision == ASAGA_PREC_F32 ? kMaxHotF32 : kMaxHot;
+    const std::string hot_range = "-1, 0 or in [1, " + std::to_string(max_hot) + "]";
     if (!std::isfinite(o->step)) return fail(nullptr, ASAGA_E_ARG, "step must be finite");
     if (o->waves < 0 || o->waves > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "waves out of range");
     if (o->lanes_per_sample != 0 && o->lanes_per_sample != 8 && o->lanes_per_sample != 16 &&
@@ -212,11 +217,11 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
         return fail(nullptr, ASAGA_E_ARG, "lanes_per_sample must be 0, 8, 16, 32 or 64");
     if (o->racy != 0 && o->racy != 1) return fail(nullptr, ASAGA_E_ARG, "racy must be 0 or 1");
     if (o->racy && o->mode != ASAGA_MODE_ASYNC) return fail(nullptr, ASAGA_E_ARG, "racy applies to async mode only");
-    if (o->hot_columns < -1 || o->hot_columns > kMaxHot)
-        return fail(nullptr, ASAGA_E_ARG, "hot_columns must be -1, 0 or in [1, 5120]");
+    if (o->hot_columns < -1 || o->hot_columns > max_hot)
+        return fail(nullptr, ASAGA_E_ARG, "hot_columns must be " + hot_range);
     if (o->flush_every < 0 || o->flush_every > (1 << 20)) return fail(nullptr, ASAGA_E_ARG, "flush_every out of range");
-    if (o->hot_tier_columns < -1 || o->hot_tier_columns > kMaxHot)
-        return fail(nullptr, ASAGA_E_ARG, "hot_tier_columns must be -1, 0 or in [1, 5120]");
+    if (o->hot_tier_columns < -1 || o->hot_tier_columns > max_hot)
+        return fail(nullptr, ASAGA_E_ARG, "hot_tier_columns must be " + hot_range);
     if (o->hot_tier_every < 0 || o->hot_tier_every > (1 << 16))
         return fail(nullptr, ASAGA_E_ARG, "hot_tier_every out of range");
     if (o->threads_per_block < 0 || o->threads_per_block > kMaxBlock || o->threads_per_block % 64 != 0)
@@ -225,8 +230,8 @@ int check_args(const asaga_problem* p, const asaga_opts* o) {
     if (o->method != ASAGA_METHOD_SAGA && o->method != ASAGA_METHOD_SVRG)
         return fail(nullptr, ASAGA_E_ARG, "bad method");
     if (o->method == ASAGA_METHOD_SVRG && o->racy) return fail(nullptr, ASAGA_E_ARG, "racy applies to SAGA only");
-    if (o->hot_reload_from < -1 || o->hot_reload_from > kMaxHot)
-        return fail(nullptr, ASAGA_E_ARG, "hot_reload_from must be -1, 0 or in [1, 5120]");
+    if (o->hot_reload_from < -1 || o->hot_reload_from > max_hot)
+        return fail(nullptr, ASAGA_E_ARG, "hot_reload_from must be " + hot_range);
     if (o->reserved != 0) return fail(nullptr, ASAGA_E_ARG, "opts.reserved must be 0");
     return ASAGA_OK;
 }
@@ -267,8 +272,32 @@ InstArgs inst_args(const Inst& I, uint64_t t0, uint64_t count) {
 }
 
 // views of an instance's state in the relabelled order
-XView x_view(const asaga_ctx* c, const Inst& I) { return c->mixed ? XView{I.xa, 4, 1} : XView{I.xa, 2, 0}; }
-XView abar_view(const Inst& I) { return XView{I.xa + 1, 2, 0}; }
+XView x_view(const asaga_ctx* c, const Inst& I) {
+    if (c->layout == kLayF32) return XView{I.xa, 2, 1};
+    return c->layout == kLayMixed ? XView{I.xa, 4, 1} : XView{I.xa, 2, 0};
+}
+XView abar_view(const asaga_ctx* c, const Inst& I) {
+    if (c->layout == kLayF32) return XView{reinterpret_cast<float*>(I.xa) + 1, 2, 1};
+    return XView{I.xa + 1, 2, 0};
+}
+
+int max_hot(const asaga_ctx* c) { return c->layout == kLayF32 ? kMaxHotF32 : kMaxHot; }
+
+// abar = (1/m) sum_j alpha_j a_j from the stored memory, in FP64 (rounded
+// once to FP32 in the FP32 layout)
+int recompute_abar(asaga_ctx* c, const Inst& I) {
+    const MatArgs A = mat(c);
+    HIPCHK(c, launch_alpha_coef(I.alpha, c->mixed, I.m, 1.0 / (double)I.m, c->tmp, c->st));
+    if (c->layout == kLayF32) {
+        HIPCHK(c, launch_fill_f64(c->vec2, 0.0, c->d, 1, c->st));
+        HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, c->vec2, 1, c->st));
+        HIPCHK(c, launch_store_slots(c->vec2, c->d, reinterpret_cast<float*>(I.xa) + 1, 2, true, c->st));
+    } else {
+        HIPCHK(c, launch_fill_f64(I.xa + 1, 0.0, c->d, 2, c->st));
+        HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.xa + 1, 2, c->st));
+    }
+    return ASAGA_OK;
+}
 
 // ---- sparse SVRG (Appendix C): randomly timed, synchronised snapshots ----
 
@@ -299,10 +328,7 @@ int svrg_snapshot(asaga_ctx* c, Inst& I) {
         HIPCHK(c, launch_dphi_coef(A, I.rows, I.m, c->z, 1.0, static_cast<double*>(I.alpha), c->st));
     }
     // abar from the stored memory (so that it is the exact average of what steps read)
-    HIPCHK(c, launch_alpha_coef(I.alpha, c->mixed, I.m, 1.0 / (double)I.m, c->tmp, c->st));
-    HIPCHK(c, launch_fill_f64(I.xa + 1, 0.0, c->d, 2, c->st));
-    HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.xa + 1, 2, c->st));
-    return ASAGA_OK;
+    return recompute_abar(c, I);
 }
 
 int zero_state(asaga_ctx* c, Inst& I) {
@@ -506,7 +532,7 @@ void pick_shape(asaga_ctx* c) {
     UpdateShape& S = c->shape;
     S.serial = c->o.mode == ASAGA_MODE_SERIAL;
     S.racy = c->o.racy != 0;
-    S.mixed = c->mixed;
+    S.layout = c->layout;
     if (S.serial) {
         // one lane group applies the samples in order; the options choose
         // which of the asynchronous kernel's paths it runs through
@@ -545,7 +571,7 @@ void pick_shape(asaga_ctx* c) {
     const int wpb = S.block / 64;
     S.waves = ((waves + wpb - 1) / wpb) * wpb;
     int hot = c->o.hot_columns;
-    if (hot == 0) hot = kMaxHot;
+    if (hot == 0) hot = max_hot(c);
     if (hot < 0 || S.racy) hot = 0;
     S.hot = (int)std::min<int64_t>(hot, c->d);
     S.flush = c->o.flush_every > 0 ? c->o.flush_every : 1;
@@ -613,7 +639,8 @@ int init_common(asaga_ctx** out, const asaga_problem* p, const asaga_opts* o, co
     c->d = p->d;
     c->loss = p->loss;
     c->val_dtype = p->val_dtype;
-    c->mixed = o->precision == ASAGA_PREC_MIXED;
+    c->layout = o->precision == ASAGA_PREC_MIXED ? kLayMixed : o->precision == ASAGA_PREC_F32 ? kLayF32 : kLayF64;
+    c->mixed = c->layout != kLayF64;
     c->svrg = o->method == ASAGA_METHOD_SVRG;
 
     auto bail = [&](int code) {
@@ -1175,7 +1202,7 @@ int asaga_get_state(asaga_ctx* c, int32_t inst, double* x_host, double* alpha_ho
         HIPCHK(c, hipStreamSynchronize(c->st));
     }
     if (abar_host) {
-        HIPCHK(c, launch_gather_view(abar_view(I), c->rank, c->d, c->vec1, c->st));
+        HIPCHK(c, launch_gather_view(abar_view(c, I), c->rank, c->d, c->vec1, c->st));
         HIPCHK(c, hipMemcpyAsync(abar_host, c->vec1, c->d * 8, hipMemcpyDeviceToHost, c->st));
         HIPCHK(c, hipStreamSynchronize(c->st));
     }
@@ -1208,12 +1235,16 @@ int asaga_set_state(asaga_ctx* c, int32_t inst, const double* x_host, const doub
     HIPCHK(c, hipStreamSynchronize(c->st));
     if (x_host) {
         HIPCHK(c, hipMemcpyAsync(c->vec1, x_host, c->d * 8, hipMemcpyHostToDevice, c->st));
-        if (c->mixed) HIPCHK(c, launch_scatter_slots(c->vec1, c->rank, c->d, I.xa, 4, true, c->st));
+        if (c->layout == kLayF32) HIPCHK(c, launch_scatter_slots(c->vec1, c->rank, c->d, I.xa, 2, true, c->st));
+        else if (c->mixed) HIPCHK(c, launch_scatter_slots(c->vec1, c->rank, c->d, I.xa, 4, true, c->st));
         else HIPCHK(c, launch_scatter_slots(c->vec1, c->rank, c->d, I.xa, 2, false, c->st));
     }
     if (abar_host) {
         HIPCHK(c, hipMemcpyAsync(c->vec2, abar_host, c->d * 8, hipMemcpyHostToDevice, c->st));
-        HIPCHK(c, launch_scatter_slots(c->vec2, c->rank, c->d, I.xa + 1, 2, false, c->st));
+        if (c->layout == kLayF32)
+            HIPCHK(c, launch_scatter_slots(c->vec2, c->rank, c->d, reinterpret_cast<float*>(I.xa) + 1, 2, true, c->st));
+        else
+            HIPCHK(c, launch_scatter_slots(c->vec2, c->rank, c->d, I.xa + 1, 2, false, c->st));
     }
     if (alpha_host) {
         if (c->mixed) {
@@ -1230,11 +1261,9 @@ int asaga_set_state(asaga_ctx* c, int32_t inst, const double* x_host, const doub
 
 int asaga_reanchor(asaga_ctx* c) {
     if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
-    const MatArgs A = mat(c);
     for (auto& I : c->inst) {
-        HIPCHK(c, launch_alpha_coef(I.alpha, c->mixed, I.m, 1.0 / (double)I.m, c->tmp, c->st));
-        HIPCHK(c, launch_fill_f64(I.xa + 1, 0.0, c->d, 2, c->st));
-        HIPCHK(c, launch_scatter(A, I.rows, I.m, c->tmp, I.xa + 1, 2, c->st));
+        int rc = recompute_abar(c, I);
+        if (rc) return rc;
     }
     return ASAGA_OK;
 }
@@ -1252,13 +1281,21 @@ int asaga_widen(asaga_ctx* c) {
     }
     for (size_t k = 0; k < c->inst.size(); ++k) {
         Inst& I = c->inst[k];
-        HIPCHK(c, launch_widen_x_slots(I.xa, c->d, c->st));
+        if (c->layout == kLayF32) {
+            // x out of the 8-byte slots, then back as FP64 pairs (abar: below)
+            HIPCHK(c, launch_copy_view(x_view(c, I), c->d, c->vec1, 1, c->st));
+            HIPCHK(c, launch_fill_f64(I.xa, 0.0, 2 * c->d, 1, c->st));
+            HIPCHK(c, launch_copy_view(XView{c->vec1, 1, 0}, c->d, I.xa, 2, c->st));
+        } else {
+            HIPCHK(c, launch_widen_x_slots(I.xa, c->d, c->st));
+        }
         HIPCHK(c, launch_widen_f32(static_cast<const float*>(I.alpha), I.m, static_cast<double*>(wide[k]), c->st));
     }
     HIPCHK(c, hipStreamSynchronize(c->st));
     for (size_t k = 0; k < c->inst.size(); ++k) c->inst[k].alpha = wide[k];
     c->mixed = false;
-    c->shape.mixed = false;
+    c->layout = kLayF64;
+    c->shape.layout = kLayF64;
     drop_graphs(c);
     // abar from the memory it averages, in FP64
     return asaga_reanchor(c);
@@ -1444,7 +1481,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
     // 1. the calibration instance alone on the device, per hot-set size
     set_active(true);
     std::vector<int> hots;
-    for (int h : {kMaxHot, 1024}) {
+    for (int h : {max_hot(c), kMaxHot, 1024}) {
         const int hot = (int)std::min<int64_t>(h, c->d);
         if (std::find(hots.begin(), hots.end(), hot) == hots.end()) hots.push_back(hot);
     }

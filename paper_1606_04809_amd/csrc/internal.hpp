@@ -2,17 +2,25 @@
 // code (kernels.hip).  Not installed; not part of the public ABI.
 //
 // Device layout of one instance's state (columns relabelled by descending
-// count, so the most-used columns are 0, 1, 2, ...):
-//   xa[2c]     x_c     FP64 (mixed precision: FP32 in the low 4 bytes)
-//   xa[2c + 1] abar_c  FP64
-// so that one 16-byte pair holds everything a sample reads and writes for a
-// column, and two adjacent lanes reach both halves with one memory request.
+// count, so the most-used columns are 0, 1, 2, ...), in an allocation of 2d
+// doubles:
+//   FP64 layout:   xa[2c] = x_c, xa[2c + 1] = abar_c (FP64)
+//   mixed layout:  x_c FP32 in the low 4 bytes of xa[2c], abar_c FP64 in xa[2c + 1]
+//   FP32 layout:   xf[2c] = x_c, xf[2c + 1] = abar_c (FP32, xf = (float*)xa; the
+//                  first 8d bytes)
+// so that one pair holds everything a sample reads and writes for a column,
+// and two adjacent lanes reach both halves with one memory request (in the
+// mixed layout the halves have different types: two requests).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace asaga {
+
+constexpr int kLayF64 = 0;
+constexpr int kLayMixed = 1;
+constexpr int kLayF32 = 2;
 
 // Per-instance arguments of the update kernels.  A single solve is one
 // instance whose row list is the identity (rows == nullptr).
@@ -80,7 +88,7 @@ struct UpdateShape {
     int tier_every;
     bool serial;      // one wave, ordered: agent-scope fence between updates
     bool racy;        // plain read-modify-write (negative control)
-    bool mixed;       // FP32 x and alpha
+    int layout;       // kLay*: state layout (FP32 x and alpha unless kLayF64)
 };
 
 // A read-only view of a vector: element v at p[v * stride], FP64 or FP32.
@@ -149,6 +157,10 @@ hipError_t launch_widen_f32(const float* in, int64_t count, double* out, hipStre
 // the FP32 x of the mixed-precision layout (low half of xa[2c]) widened in place to FP64
 hipError_t launch_widen_x_slots(double* xa, int64_t d, hipStream_t st);
 hipError_t launch_narrow_f64(const double* in, int64_t count, float* out, hipStream_t st);
+// out[c * out_stride] = x[c], c < d  (a view copied to FP64)
+hipError_t launch_copy_view(XView x, int64_t d, double* out, int64_t out_stride, hipStream_t st);
+// slot[c * stride] = in[c], c < d, as FP32 (f32) or FP64
+hipError_t launch_store_slots(const double* in, int64_t d, void* slot, int64_t stride, bool f32, hipStream_t st);
 
 hipError_t launch_sample_stream(uint64_t seed, uint64_t t0, int64_t count, int64_t n, int64_t* out, hipStream_t st);
 // memory-side request probe: blocks x 256 threads, iters operations per lane

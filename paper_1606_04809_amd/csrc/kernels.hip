@@ -49,8 +49,10 @@
 namespace asaga {
 
 // LDS of a workgroup with a hot set of H columns, both halves interleaved
-// like xa:  lds[0, 2H)   view: the global (x, abar) values at the last flush
-//           lds[2H, 4H)  pend: the workgroup's own additions since then
+// like the state:  [0, 2H)   view: the global (x, abar) values at the last flush
+//                  [2H, 4H)  pend: the workgroup's own additions since then
+// in FP64 (FP64 and mixed layouts) or FP32 (FP32 layout: 16 bytes per column,
+// so twice the columns fit).
 extern __shared__ double lds[];
 
 // ---------------------------------------------------------------------------
@@ -93,19 +95,32 @@ __device__ __forceinline__ double dphi(double z, double b, int loss) {
     return -b / (1.0 + exp(m));
 }
 
-// Shared-state reads: relaxed atomics at agent scope (no ordering; the value
-// comes from the device-coherent level).  comp 0 reads x_c, comp 1 abar_c.
-template <bool MIXED>
-__device__ __forceinline__ double load_slot(const double* xa, int32_t c, int comp) {
-    const uint64_t bits = __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<double*>(xa)) + 2 * (int64_t)c + comp,
-                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (MIXED && comp == 0) return (double)__uint_as_float((uint32_t)bits);
-    return __longlong_as_double((long long)bits);
+// State layouts (kLay* in internal.hpp): x and alpha are FP32 in the mixed
+// and FP32 layouts; abar is FP32 too in the FP32 layout, where a column's
+// (x, abar) pair takes 8 bytes instead of 16.
+template <int LAY>
+constexpr bool kX32 = LAY != kLayF64;
+template <int LAY>
+constexpr bool kS32 = LAY == kLayF32;
+
+// hot-set LDS entry i (view or pending half) in the layout's precision
+template <int LAY>
+__device__ __forceinline__ double lds_get(int i) {
+    if constexpr (kS32<LAY>) return (double)reinterpret_cast<const float*>(lds)[i];
+    else return lds[i];
 }
 
-template <bool MIXED>
+template <int LAY>
+__device__ __forceinline__ void lds_add(int i, double w) {
+    if constexpr (kS32<LAY>) atomicAdd(reinterpret_cast<float*>(lds) + i, (float)w);
+    else atomicAdd(&lds[i], w);
+}
+
+// Shared-state reads: relaxed atomics at agent scope (no ordering; the value
+// comes from the device-coherent level).
+template <int LAY>
 __device__ __forceinline__ double load_alpha(const void* alpha, int64_t j) {
-    if constexpr (MIXED)
+    if constexpr (kX32<LAY>)
         return (double)__hip_atomic_load(const_cast<float*>(static_cast<const float*>(alpha)) + j, __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
     else
@@ -125,21 +140,24 @@ __device__ __forceinline__ void add_global(T* p, T v) {
 }
 
 // add w to slot (c, comp) of the state: LDS pending sum for hot columns,
-// global atomic otherwise
-template <bool RACY, bool MIXED>
+// global atomic otherwise.  In the FP32 layout both lanes of a pair add to
+// the same 8 bytes with the same instruction: one memory request.
+template <bool RACY, int LAY>
 __device__ __forceinline__ void add_slot(double* xa, int32_t c, int comp, int hot, double w) {
     if (c < hot) {
-        atomicAdd(&lds[2 * hot + 2 * c + comp], w);
-    } else if (MIXED && comp == 0) {
+        lds_add<LAY>(2 * hot + 2 * c + comp, w);
+    } else if constexpr (kS32<LAY>) {
+        add_global<RACY, float>(reinterpret_cast<float*>(xa) + 2 * (int64_t)c + comp, (float)w);
+    } else if (LAY == kLayMixed && comp == 0) {
         add_global<RACY, float>(reinterpret_cast<float*>(xa + 2 * (int64_t)c), (float)w);
     } else {
         add_global<RACY, double>(xa + 2 * (int64_t)c + comp, w);
     }
 }
 
-template <bool RACY, bool MIXED>
+template <bool RACY, int LAY>
 __device__ __forceinline__ void add_alpha(void* alpha, int64_t j, double delta) {
-    if constexpr (MIXED)
+    if constexpr (kX32<LAY>)
         add_global<RACY, float>(static_cast<float*>(alpha) + j, (float)delta);
     else
         add_global<RACY, double>(static_cast<double*>(alpha) + j, delta);
@@ -171,16 +189,24 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t state_rsrc(const double* xa, i
 
 // Columns below `hot` are served from LDS: their load gets an offset past
 // the descriptor's range, which the hardware drops (it returns zeros and
-// sends no request), so the read needs no branch.
-template <bool MIXED>
+// sends no request), so the read needs no branch.  The FP32 layout's pair
+// is one 8-byte load.
+template <int LAY>
 __device__ __forceinline__ Pair load_pair(__amdgpu_buffer_rsrc_t r, int32_t c, int hot) {
     constexpr int kSC1 = 16;
-    const int off = c >= hot ? c * 16 : (int)0x7ffffff0;
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kSC1);
     Pair p;
-    if (MIXED) p.x = (double)__uint_as_float(v[0]);
-    else p.x = __longlong_as_double((long long)(((uint64_t)v[1] << 32) | v[0]));
-    p.a = __longlong_as_double((long long)(((uint64_t)v[3] << 32) | v[2]));
+    if constexpr (kS32<LAY>) {
+        const int off = c >= hot ? c * 8 : (int)0x7ffffff0;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kSC1);
+        p.x = (double)__uint_as_float(v[0]);
+        p.a = (double)__uint_as_float(v[1]);
+    } else {
+        const int off = c >= hot ? c * 16 : (int)0x7ffffff0;
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kSC1);
+        if (LAY == kLayMixed) p.x = (double)__uint_as_float(v[0]);
+        else p.x = __longlong_as_double((long long)(((uint64_t)v[1] << 32) | v[0]));
+        p.a = __longlong_as_double((long long)(((uint64_t)v[3] << 32) | v[2]));
+    }
     return p;
 }
 
@@ -191,7 +217,7 @@ struct RowRef {
     double b, alpha;
 };
 
-template <bool SERIAL, bool MIXED>
+template <bool SERIAL, int LAY>
 __device__ __forceinline__ RowRef row_ref(const MatArgs& A, const InstArgs& I, uint64_t t) {
     RowRef r;
     r.j = sample_index(I.seed, t, I.m);
@@ -199,7 +225,7 @@ __device__ __forceinline__ RowRef row_ref(const MatArgs& A, const InstArgs& I, u
     r.rs = A.rowptr[r.i];
     r.re = A.rowptr[r.i + 1];
     r.b = A.b[r.i];
-    r.alpha = SERIAL ? 0.0 : load_alpha<MIXED>(I.alpha, r.j);
+    r.alpha = SERIAL ? 0.0 : load_alpha<LAY>(I.alpha, r.j);
     return r;
 }
 
@@ -211,7 +237,7 @@ __device__ __forceinline__ RowRef row_ref(const MatArgs& A, const InstArgs& I, u
 // P * G / 2 entries are held in registers between the two phases, with all
 // their loads issued together; longer rows are processed in chunks and read
 // again for the write phase.
-template <int G, int P, bool SERIAL, bool RACY, bool MIXED, typename VT>
+template <int G, int P, bool SERIAL, bool RACY, int LAY, typename VT>
 __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I, const RowRef& rr, int gl, int hot,
                                              int* flag) {
     constexpr int E = G / 2;
@@ -236,7 +262,7 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
         }
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const Pair pr = load_pair<MIXED>(rsrc, cc[p], hot);
+            const Pair pr = load_pair<LAY>(rsrc, cc[p], hot);
             xs[p] = pr.x;
             as[p] = pr.a;
             dd[p] = I.D[cc[p]];
@@ -247,8 +273,8 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
             if (q < len) {
                 if (cc[p] < hot) {
                     const int h = 2 * cc[p];
-                    xs[p] = lds[h] + lds[2 * hot + h];
-                    as[p] = lds[h + 1] + lds[2 * hot + h + 1];
+                    xs[p] = lds_get<LAY>(h) + lds_get<LAY>(2 * hot + h);
+                    as[p] = lds_get<LAY>(h + 1) + lds_get<LAY>(2 * hot + h + 1);
                 }
                 if (comp == 0) zp += vv[p] * xs[p];
             }
@@ -256,8 +282,8 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
     } else {
         for (int64_t k = rr.rs + gl; k < rr.re; k += G) {
             const int32_t c = A.colidx[k];
-            double x = load_pair<MIXED>(rsrc, c, hot).x;
-            if (c < hot) x = lds[2 * c] + lds[2 * hot + 2 * c];
+            double x = load_pair<LAY>(rsrc, c, hot).x;
+            if (c < hot) x = lds_get<LAY>(2 * c) + lds_get<LAY>(2 * hot + 2 * c);
             zp += widen(val[k]) * x;
         }
     }
@@ -265,8 +291,8 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
 
     // scalar gradient change against the memory
     double g = dphi(z, rr.b, A.loss);
-    if constexpr (MIXED) g = (double)(float)g;  // stored memory is FP32
-    const double al = SERIAL ? load_alpha<MIXED>(I.alpha, rr.j) : rr.alpha;
+    if constexpr (kX32<LAY>) g = (double)(float)g;  // stored memory is FP32
+    const double al = SERIAL ? load_alpha<LAY>(I.alpha, rr.j) : rr.alpha;
     const double delta = g - al;
     if (gl == 0 && !isfinite(delta)) *flag = 1;
     // What the memory entry gains: with FP32 memory the atomic addition
@@ -275,7 +301,7 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
     // so that it stays the average of the stored memory (exactly when no
     // other sample changed alpha_j between this read and the addition).
     double dmem = delta;
-    if constexpr (MIXED) dmem = (double)((float)al + (float)delta) - al;
+    if constexpr (kX32<LAY>) dmem = (double)((float)al + (float)delta) - al;
 
     // write phase: x_c += -gamma (delta a_c + D_c (abar_c + lambda x_hat_c)) on even lanes,
     //              abar_c += dmem a_c / m on odd lanes
@@ -288,31 +314,35 @@ __device__ __forceinline__ void apply_update(const MatArgs& A, const InstArgs& I
             const int64_t q = (int64_t)p * E + e;
             if (q < len && writes) {
                 const double w = comp == 0 ? -gam * (delta * vv[p] + dd[p] * (as[p] + lam * xs[p])) : dm * vv[p];
-                add_slot<RACY, MIXED>(I.xa, cc[p], comp, hot, w);
+                add_slot<RACY, LAY>(I.xa, cc[p], comp, hot, w);
             }
         }
     } else {
         for (int64_t k = rr.rs + e; k < rr.re; k += E) {
             const int32_t c = A.colidx[k];
             const double v = widen(val[k]);
-            Pair pr = load_pair<MIXED>(rsrc, c, hot);
+            Pair pr = load_pair<LAY>(rsrc, c, hot);
             if (c < hot) {
-                pr.x = lds[2 * c] + lds[2 * hot + 2 * c];
-                pr.a = lds[2 * c + 1] + lds[2 * hot + 2 * c + 1];
+                pr.x = lds_get<LAY>(2 * c) + lds_get<LAY>(2 * hot + 2 * c);
+                pr.a = lds_get<LAY>(2 * c + 1) + lds_get<LAY>(2 * hot + 2 * c + 1);
             }
             const double w = comp == 0 ? -gam * (delta * v + I.D[c] * (pr.a + lam * pr.x)) : dm * v;
-            if (writes) add_slot<RACY, MIXED>(I.xa, c, comp, hot, w);
+            if (writes) add_slot<RACY, LAY>(I.xa, c, comp, hot, w);
         }
     }
-    if (gl == 0 && !I.frozen) add_alpha<RACY, MIXED>(I.alpha, rr.j, delta);
+    if (gl == 0 && !I.frozen) add_alpha<RACY, LAY>(I.alpha, rr.j, delta);
     if constexpr (SERIAL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
 }
 
 // The global value of slot q of the interleaved state (x in FP32 for the
-// mixed layout), read at the device-coherent level.
-template <bool MIXED>
+// mixed layout, both halves for the FP32 layout), read at the
+// device-coherent level.
+template <int LAY>
 __device__ __forceinline__ double load_slot(const double* xa, int q) {
-    if (MIXED && (q & 1) == 0)
+    if constexpr (kS32<LAY>)
+        return (double)__hip_atomic_load(reinterpret_cast<float*>(const_cast<double*>(xa)) + q, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+    if (LAY == kLayMixed && (q & 1) == 0)
         return (double)__hip_atomic_load(reinterpret_cast<float*>(const_cast<double*>(xa) + q), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
     return __hip_atomic_load(const_cast<double*>(xa) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -328,14 +358,40 @@ __device__ __forceinline__ double load_slot(const double* xa, int q) {
 // other workgroups apply about W of its updates, each a step of about
 // gamma D_v: without a reload, the view of the rarer hot columns lags by
 // about W D_v samples.)  Consecutive threads take consecutive slots, so each
-// wave instruction covers 512 contiguous bytes (8 lines).
-template <bool MIXED>
+// wave instruction covers 512 contiguous bytes (8 lines; FP32 layout: 256
+// bytes, 4 lines).
+//
+// FP32 layout: a slot is flushed when its pending sum exceeds half a unit
+// in the last place of the view.  The returning atomic gives the old value,
+// so the rounding error of the addition (TwoSum of old and the pending sum)
+// is known exactly; it stays pending and rides along with the workgroup's
+// next contribution to the slot, so the hot columns' FP32 sums are
+// compensated.  What is still pending at the end of a launch (at most half
+// a unit in the last place per slot and workgroup) is dropped.
+template <int LAY>
 __device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto, int reload_from) {
+    if constexpr (kS32<LAY>) {
+        float* lf = reinterpret_cast<float*>(lds);
+        float* gs = reinterpret_cast<float*>(xa);
+        for (int q = threadIdx.x; q < 2 * upto; q += blockDim.x) {
+            const float w = lf[2 * hot + q];
+            if (fabsf(w) > fabsf(lf[q]) * 0x1p-24f) {
+                const float old = __hip_atomic_fetch_add(gs + q, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const float s = old + w;
+                const float bv = s - old;
+                lf[q] = s;
+                lf[2 * hot + q] = (old - (s - bv)) + (w - bv);
+            } else if (q >= 2 * reload_from) {
+                lf[q] = __hip_atomic_load(gs + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        return;
+    }
     for (int q = threadIdx.x; q < 2 * upto; q += blockDim.x) {
         const double w = lds[2 * hot + q];
         if (w != 0.0) {
             double now;
-            if (MIXED && (q & 1) == 0)
+            if (LAY == kLayMixed && (q & 1) == 0)
                 now = (double)(__hip_atomic_fetch_add(reinterpret_cast<float*>(xa + q), (float)w, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT) + (float)w);
             else
@@ -343,16 +399,21 @@ __device__ __forceinline__ void flush_and_refresh(double* xa, int hot, int upto,
             lds[q] = now;
             lds[2 * hot + q] = 0.0;
         } else if (q >= 2 * reload_from) {
-            lds[q] = load_slot<MIXED>(xa, q);
+            lds[q] = load_slot<LAY>(xa, q);
         }
     }
 }
 
-template <bool MIXED>
+template <int LAY>
 __device__ __forceinline__ void load_view(const double* xa, int hot) {
     for (int q = threadIdx.x; q < 2 * hot; q += blockDim.x) {
-        lds[q] = load_slot<MIXED>(xa, q);
-        lds[2 * hot + q] = 0.0;
+        if constexpr (kS32<LAY>) {
+            reinterpret_cast<float*>(lds)[q] = (float)load_slot<LAY>(xa, q);
+            reinterpret_cast<float*>(lds)[2 * hot + q] = 0.0f;
+        } else {
+            lds[q] = load_slot<LAY>(xa, q);
+            lds[2 * hot + q] = 0.0;
+        }
     }
 }
 
@@ -364,7 +425,7 @@ __device__ __forceinline__ void load_view(const double* xa, int hot) {
 // `tier` hot columns, and all hot columns every `tier_every` rounds (then
 // reloading the view of the slots from `reload_from` on that it did not
 // write) and at the end of the launch.
-template <int G, int P, bool SERIAL, bool RACY, bool MIXED, typename VT>
+template <int G, int P, bool SERIAL, bool RACY, int LAY, typename VT>
 __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, uint64_t t0, uint64_t slot,
                                           uint64_t slots, HotArgs H, int* flag) {
     const int gl = threadIdx.x & (G - 1);
@@ -373,12 +434,12 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
     // a group with no sample and no workgroup flush to take part in
     if (hot == 0 && slot >= I.count) return;
     if (hot > 0) {
-        load_view<MIXED>(I.xa, hot);
+        load_view<LAY>(I.xa, hot);
         __syncthreads();
     }
     const uint64_t round = hot > 0 ? (uint64_t)H.flush : kmax;
     RowRef cur{0, 0, 0, 0, 0.0, 0.0};
-    if (slot < I.count) cur = row_ref<SERIAL, MIXED>(A, I, t0 + slot);
+    if (slot < I.count) cur = row_ref<SERIAL, LAY>(A, I, t0 + slot);
     uint64_t r = 0;
     for (uint64_t k0 = 0; k0 < kmax; k0 += round, ++r) {
         const uint64_t k1 = k0 + round < kmax ? k0 + round : kmax;
@@ -386,14 +447,14 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
             const uint64_t s = slot + k * slots;
             const uint64_t s2 = s + slots;
             RowRef nxt{0, 0, 0, 0, 0.0, 0.0};
-            if (s2 < I.count) nxt = row_ref<SERIAL, MIXED>(A, I, t0 + s2);
+            if (s2 < I.count) nxt = row_ref<SERIAL, LAY>(A, I, t0 + s2);
             // sampled overlap log: clock at the read, and once the sample's
             // global writes are visible device-wide
             const bool logged = I.tau_log != nullptr && s < I.count &&
                                 splitmix64(0x7A05EEDull, t0 + s) % kTauEvery == 0;
             long long t_read = 0;
             if (logged) t_read = wall_clock64();
-            if (s < I.count) apply_update<G, P, SERIAL, RACY, MIXED, VT>(A, I, cur, gl, hot, flag);
+            if (s < I.count) apply_update<G, P, SERIAL, RACY, LAY, VT>(A, I, cur, gl, hot, flag);
             if (logged) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 const long long t_done = wall_clock64();
@@ -413,7 +474,7 @@ __device__ __forceinline__ void run_slots(const MatArgs& A, const InstArgs& I, u
             const bool all = last || (r + 1) % (uint64_t)H.tier_every == 0;
             __syncthreads();
             const int upto = all ? hot : H.tier;
-            flush_and_refresh<MIXED>(I.xa, hot, upto, all && !last && I.reload_from < upto ? I.reload_from : upto);
+            flush_and_refresh<LAY>(I.xa, hot, upto, all && !last && I.reload_from < upto ? I.reload_from : upto);
             __syncthreads();
         }
     }
@@ -444,16 +505,16 @@ __device__ __forceinline__ void slot_range(uint64_t rank, uint64_t n_blocks, uin
     }
 }
 
-template <int G, bool SERIAL, bool RACY, bool MIXED, typename VT>
+template <int G, bool SERIAL, bool RACY, int LAY, typename VT>
 __global__ void __launch_bounds__(1024) k_update(MatArgs A, InstArgs I, HotArgs H, int* flag) {
     uint64_t slot, slots;
     slot_range<G, SERIAL>(blockIdx.x, gridDim.x, I.count, &slot, &slots);
-    run_slots<G, kPasses, SERIAL, RACY, MIXED, VT>(A, I, I.t0, slot, slots, H, flag);
+    run_slots<G, kPasses, SERIAL, RACY, LAY, VT>(A, I, I.t0, slot, slots, H, flag);
 }
 
 // Many instances in one persistent grid: the block map says which instance
 // each workgroup serves and as which of that instance's workgroups.
-template <int G, bool SERIAL, bool MIXED, typename VT>
+template <int G, bool SERIAL, int LAY, typename VT>
 __global__ void __launch_bounds__(1024) k_update_batched(MatArgs A, const InstArgs* insts, const BlockMap* map,
                                                         uint64_t epoch, HotArgs H, int* flag) {
     const BlockMap bm = map[blockIdx.x];
@@ -462,14 +523,16 @@ __global__ void __launch_bounds__(1024) k_update_batched(MatArgs A, const InstAr
     if (I.count == 0 || bm.rank >= I.blocks) return;  // instance switched off: its state stays as it is
     uint64_t slot, slots;
     slot_range<G, SERIAL>(bm.rank, I.blocks, I.count, &slot, &slots);
-    run_slots<G, kPasses, SERIAL, false, MIXED, VT>(A, I, I.t0 + epoch * I.count, slot, slots, H, flag);
+    run_slots<G, kPasses, SERIAL, false, LAY, VT>(A, I, I.t0 + epoch * I.count, slot, slots, H, flag);
 }
 
 // ---------------------------------------------------------------------------
 // launchers for the update kernels
 // ---------------------------------------------------------------------------
 
-size_t update_lds_bytes(const UpdateShape& S) { return (size_t)S.hot * 4 * sizeof(double); }
+size_t update_lds_bytes(const UpdateShape& S) {
+    return (size_t)S.hot * 4 * (S.layout == kLayF32 ? sizeof(float) : sizeof(double));
+}
 
 static HotArgs hot_args(const UpdateShape& S) {
     HotArgs H;
@@ -480,93 +543,98 @@ static HotArgs hot_args(const UpdateShape& S) {
     return H;
 }
 
-template <int G, bool SERIAL, bool MIXED, typename VT>
+template <int G, bool SERIAL, int LAY, typename VT>
 static hipError_t launch_update_g(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int blocks, int* flag,
                                   hipStream_t st) {
     const size_t lds = update_lds_bytes(S);
     if (lds > 65536) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update<G, SERIAL, false, MIXED, VT>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update<G, SERIAL, false, LAY, VT>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_update<G, SERIAL, false, MIXED, VT><<<blocks, S.block, lds, st>>>(A, I, hot_args(S), flag);
+    k_update<G, SERIAL, false, LAY, VT><<<blocks, S.block, lds, st>>>(A, I, hot_args(S), flag);
     return hipGetLastError();
 }
 
-template <bool SERIAL, bool MIXED, typename VT>
+template <bool SERIAL, int LAY, typename VT>
 static hipError_t launch_update_s(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int blocks, int* flag,
                                   hipStream_t st) {
     switch (S.lanes) {
-        case 64: return launch_update_g<64, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
-        case 32: return launch_update_g<32, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
-        case 16: return launch_update_g<16, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
-        case 8: return launch_update_g<8, SERIAL, MIXED, VT>(A, I, S, blocks, flag, st);
+        case 64: return launch_update_g<64, SERIAL, LAY, VT>(A, I, S, blocks, flag, st);
+        case 32: return launch_update_g<32, SERIAL, LAY, VT>(A, I, S, blocks, flag, st);
+        case 16: return launch_update_g<16, SERIAL, LAY, VT>(A, I, S, blocks, flag, st);
+        case 8: return launch_update_g<8, SERIAL, LAY, VT>(A, I, S, blocks, flag, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <bool MIXED, typename VT>
+template <int LAY, typename VT>
 static hipError_t launch_updates_t(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag,
                                    hipStream_t st) {
     if (I.count == 0) return hipSuccess;
     // ordered: one workgroup, whose first lane group applies the samples
-    if (S.serial) return launch_update_s<true, MIXED, VT>(A, I, S, 1, flag, st);
+    if (S.serial) return launch_update_s<true, LAY, VT>(A, I, S, 1, flag, st);
     const int threads = S.block;
     const int blocks = (S.waves * 64 + threads - 1) / threads;
     if (S.racy) {
         const HotArgs none{0, 1, 0, 1};
         switch (S.lanes) {
-            case 64: k_update<64, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
-            case 32: k_update<32, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
-            case 16: k_update<16, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
-            case 8: k_update<8, false, true, MIXED, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 64: k_update<64, false, true, LAY, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 32: k_update<32, false, true, LAY, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 16: k_update<16, false, true, LAY, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
+            case 8: k_update<8, false, true, LAY, VT><<<blocks, threads, 0, st>>>(A, I, none, flag); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     }
-    return launch_update_s<false, MIXED, VT>(A, I, S, blocks, flag, st);
+    return launch_update_s<false, LAY, VT>(A, I, S, blocks, flag, st);
 }
 
-hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag, hipStream_t st) {
-    switch (A.val_dtype) {
-        case ASAGA_VAL_F64:
-            return S.mixed ? launch_updates_t<true, double>(A, I, S, flag, st)
-                           : launch_updates_t<false, double>(A, I, S, flag, st);
-        case ASAGA_VAL_F32:
-            return S.mixed ? launch_updates_t<true, float>(A, I, S, flag, st)
-                           : launch_updates_t<false, float>(A, I, S, flag, st);
-        case ASAGA_VAL_BF16:
-            return S.mixed ? launch_updates_t<true, uint16_t>(A, I, S, flag, st)
-                           : launch_updates_t<false, uint16_t>(A, I, S, flag, st);
+template <typename VT>
+static hipError_t launch_updates_v(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag,
+                                   hipStream_t st) {
+    switch (S.layout) {
+        case kLayF64: return launch_updates_t<kLayF64, VT>(A, I, S, flag, st);
+        case kLayMixed: return launch_updates_t<kLayMixed, VT>(A, I, S, flag, st);
+        case kLayF32: return launch_updates_t<kLayF32, VT>(A, I, S, flag, st);
     }
     return hipErrorInvalidValue;
 }
 
-template <int G, bool SERIAL, bool MIXED, typename VT>
+hipError_t launch_updates(const MatArgs& A, const InstArgs& I, const UpdateShape& S, int* flag, hipStream_t st) {
+    switch (A.val_dtype) {
+        case ASAGA_VAL_F64: return launch_updates_v<double>(A, I, S, flag, st);
+        case ASAGA_VAL_F32: return launch_updates_v<float>(A, I, S, flag, st);
+        case ASAGA_VAL_BF16: return launch_updates_v<uint16_t>(A, I, S, flag, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int G, bool SERIAL, int LAY, typename VT>
 static hipError_t launch_batched_gs(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
                                     uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
     const size_t lds = update_lds_bytes(S);
     if (lds > 65536) {
         const hipError_t e =
-            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_batched<G, SERIAL, MIXED, VT>),
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_update_batched<G, SERIAL, LAY, VT>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_update_batched<G, SERIAL, MIXED, VT><<<n_blocks, S.block, lds, st>>>(A, insts, map, epoch, hot_args(S), flag);
+    k_update_batched<G, SERIAL, LAY, VT><<<n_blocks, S.block, lds, st>>>(A, insts, map, epoch, hot_args(S), flag);
     return hipGetLastError();
 }
 
-template <int G, bool MIXED, typename VT>
+template <int G, int LAY, typename VT>
 static hipError_t launch_batched_g(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
                                    uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
-    return S.serial ? launch_batched_gs<G, true, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st)
-                    : launch_batched_gs<G, false, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+    return S.serial ? launch_batched_gs<G, true, LAY, VT>(A, insts, map, n_blocks, epoch, S, flag, st)
+                    : launch_batched_gs<G, false, LAY, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
 }
 
-template <int G, bool MIXED, typename VT>
+template <int G, int LAY, typename VT>
 static int resident_g(const UpdateShape& S) {
     const size_t lds = update_lds_bytes(S);
-    const void* fn = reinterpret_cast<const void*>(&k_update_batched<G, false, MIXED, VT>);
+    const void* fn = reinterpret_cast<const void*>(&k_update_batched<G, false, LAY, VT>);
     if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return 0;
     int per_cu = 0;
@@ -574,51 +642,66 @@ static int resident_g(const UpdateShape& S) {
     return per_cu * device_cu_count();
 }
 
-template <bool MIXED, typename VT>
+template <int LAY, typename VT>
 static hipError_t launch_batched_t(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
                                    uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
     switch (S.lanes) {
-        case 64: return launch_batched_g<64, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
-        case 32: return launch_batched_g<32, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
-        case 16: return launch_batched_g<16, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
-        case 8: return launch_batched_g<8, MIXED, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 64: return launch_batched_g<64, LAY, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 32: return launch_batched_g<32, LAY, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 16: return launch_batched_g<16, LAY, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case 8: return launch_batched_g<8, LAY, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <bool MIXED, typename VT>
+template <int LAY, typename VT>
 static int resident_t(const UpdateShape& S) {
     switch (S.lanes) {
-        case 64: return resident_g<64, MIXED, VT>(S);
-        case 32: return resident_g<32, MIXED, VT>(S);
-        case 16: return resident_g<16, MIXED, VT>(S);
-        case 8: return resident_g<8, MIXED, VT>(S);
+        case 64: return resident_g<64, LAY, VT>(S);
+        case 32: return resident_g<32, LAY, VT>(S);
+        case 16: return resident_g<16, LAY, VT>(S);
+        case 8: return resident_g<8, LAY, VT>(S);
         default: return 0;
     }
+}
+
+template <typename VT>
+static hipError_t launch_batched_v(const MatArgs& A, const InstArgs* insts, const BlockMap* map, int n_blocks,
+                                   uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
+    switch (S.layout) {
+        case kLayF64: return launch_batched_t<kLayF64, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case kLayMixed: return launch_batched_t<kLayMixed, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+        case kLayF32: return launch_batched_t<kLayF32, VT>(A, insts, map, n_blocks, epoch, S, flag, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_updates_batched(const MatArgs& A, const InstArgs* dev_insts, const BlockMap* dev_map,
                                   int n_blocks, uint64_t epoch, const UpdateShape& S, int* flag, hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
     switch (A.val_dtype) {
-        case ASAGA_VAL_F64:
-            return S.mixed ? launch_batched_t<true, double>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st)
-                           : launch_batched_t<false, double>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
-        case ASAGA_VAL_F32:
-            return S.mixed ? launch_batched_t<true, float>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st)
-                           : launch_batched_t<false, float>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
-        case ASAGA_VAL_BF16:
-            return S.mixed ? launch_batched_t<true, uint16_t>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st)
-                           : launch_batched_t<false, uint16_t>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
+        case ASAGA_VAL_F64: return launch_batched_v<double>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
+        case ASAGA_VAL_F32: return launch_batched_v<float>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
+        case ASAGA_VAL_BF16: return launch_batched_v<uint16_t>(A, dev_insts, dev_map, n_blocks, epoch, S, flag, st);
     }
     return hipErrorInvalidValue;
 }
 
+template <typename VT>
+static int resident_v(const UpdateShape& S) {
+    switch (S.layout) {
+        case kLayF64: return resident_t<kLayF64, VT>(S);
+        case kLayMixed: return resident_t<kLayMixed, VT>(S);
+        case kLayF32: return resident_t<kLayF32, VT>(S);
+    }
+    return 0;
+}
+
 int batched_resident_blocks(const UpdateShape& S, int32_t val_dtype) {
     switch (val_dtype) {
-        case ASAGA_VAL_F64: return S.mixed ? resident_t<true, double>(S) : resident_t<false, double>(S);
-        case ASAGA_VAL_F32: return S.mixed ? resident_t<true, float>(S) : resident_t<false, float>(S);
-        case ASAGA_VAL_BF16: return S.mixed ? resident_t<true, uint16_t>(S) : resident_t<false, uint16_t>(S);
+        case ASAGA_VAL_F64: return resident_v<double>(S);
+        case ASAGA_VAL_F32: return resident_v<float>(S);
+        case ASAGA_VAL_BF16: return resident_v<uint16_t>(S);
     }
     return 0;
 }
@@ -1042,6 +1125,28 @@ __global__ void k_widen(const float* in, int64_t count, double* out) {
 __global__ void k_narrow(const double* in, int64_t count, float* out) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (int64_t)gridDim.x * blockDim.x)
         out[k] = (float)in[k];
+}
+
+__global__ void k_copy_view(XView x, int64_t d, double* out, int64_t out_stride) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < d; c += (int64_t)gridDim.x * blockDim.x)
+        out[c * out_stride] = xget(x, c);
+}
+
+hipError_t launch_copy_view(XView x, int64_t d, double* out, int64_t out_stride, hipStream_t st) {
+    k_copy_view<<<grid_for(d, 256), 256, 0, st>>>(x, d, out, out_stride);
+    return hipGetLastError();
+}
+
+__global__ void k_store_slots(const double* in, int64_t d, void* slot, int64_t stride, int f32) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < d; c += (int64_t)gridDim.x * blockDim.x) {
+        if (f32) static_cast<float*>(slot)[c * stride] = (float)in[c];
+        else static_cast<double*>(slot)[c * stride] = in[c];
+    }
+}
+
+hipError_t launch_store_slots(const double* in, int64_t d, void* slot, int64_t stride, bool f32, hipStream_t st) {
+    k_store_slots<<<grid_for(d, 256), 256, 0, st>>>(in, d, slot, stride, f32 ? 1 : 0);
+    return hipGetLastError();
 }
 
 // x_c stored as FP32 in the low half of slot xa[2c] -> FP64 in the whole slot

@@ -197,3 +197,31 @@ def test_ordered_mixed_precision_memory_average_is_exact():
         say(f"ordered mixed {shape.get('hot_columns', 0)} hot: invariant {inv:.1e}, x vs FP64 oracle {dx:.1e}")
         assert inv <= 1e-12
         assert dx <= 1e-4
+
+
+@pytest.mark.parametrize("lanes", [16, 64])
+def test_ordered_f32_state_follows_the_oracle_to_fp32_rounding(lanes):
+    """FP32 x, alpha and abar (8-byte slots), through every hot-set path
+    (tiered flush, refresh, reload, FP32 pending sums with the flush's
+    rounding error carried to the next flush): the iterates and the memory
+    follow the FP64 oracle's to FP32 rounding, and abar stays the average of
+    the stored memory to FP32 rounding, with and without the hot set; the
+    hot-set run and the run without it agree to FP32 rounding too."""
+    p = datagen.config2(n=5000, d=2500)
+    sv = oracle.SparseSaga(p)
+    sv.epochs(4)
+    runs = {}
+    for shape in (dict(lanes_per_sample=lanes), dict(HOT, lanes_per_sample=lanes)):
+        with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, precision=A.ASAGA_PREC_F32, **shape) as g:
+            g.epochs(4)
+            x, alpha, abar, t = g.get_state()
+        assert t == sv.state.t
+        inv = rel_err(abar, oracle.SparseSaga(p).memory_average(alpha))
+        dx, da = rel_err(x, sv.state.x), rel_err(alpha, sv.state.alpha)
+        hot = shape.get("hot_columns", 0)
+        say(f"ordered f32, {lanes} lanes, {hot} hot: invariant {inv:.1e}, x vs FP64 oracle {dx:.1e}, "
+            f"alpha {da:.1e}")
+        assert inv <= 1e-5
+        assert dx <= 1e-4 and da <= 1e-4
+        runs[hot] = x
+    assert rel_err(runs[512], runs[0]) <= 1e-4

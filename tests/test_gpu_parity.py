@@ -18,6 +18,9 @@ def say(*a):
     print(*a, flush=True, file=sys.stderr)
 
 
+PRECISIONS = {"f64": A.ASAGA_PREC_F64, "mixed": A.ASAGA_PREC_MIXED, "f32": A.ASAGA_PREC_F32}
+
+
 def ragged_problem(seed=0, n=300, d=700, loss=datagen.LOGISTIC, lam=None):
     """Rows of very uneven length: 1 .. 400 entries (several rows longer than
     the 128 entries kept in registers), columns uniform."""
@@ -332,11 +335,13 @@ def test_async_config2_benchmarked_shape_reaches_1e9(golden):
         assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-11
 
 
-def test_batched_config5_all_160_reach_1e9(golden):
+@pytest.mark.parametrize("precision", ["mixed", "f32"])
+def test_batched_config5_all_160_reach_1e9(golden, precision):
     """The lambda path x folds batch as the benchmark runs it: 160 instances
-    over the bfloat16 config-2 matrix, mixed precision, autotuned step law,
-    automatic workgroups, each switched off at 1e-9 of its certified optimum;
-    the last instances running (lambda = 1e-8) must converge too."""
+    over the bfloat16 config-2 matrix, FP32 x and alpha (abar FP64, or FP32
+    with compensated hot-column flushes), autotuned step law, automatic
+    workgroups, each switched off at 1e-9 of its certified optimum; the last
+    instances running (lambda = 1e-8) must converge too."""
     import hashlib
     B = datagen.config5()
     h = hashlib.sha256(B.problem.digest().encode())
@@ -345,10 +350,12 @@ def test_batched_config5_all_160_reach_1e9(golden):
     assert h.hexdigest() == golden["config5"]["digest"]
     fstar = np.array([e["f_lower"] for e in sorted(golden["config5"]["instances"], key=lambda e: e["k"])])
     ni = B.n_inst
-    with A.from_problem(B.problem, bf16=True, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED,
+    prec = PRECISIONS[precision]
+    with A.from_problem(B.problem, bf16=True, mode=A.ASAGA_MODE_ASYNC, precision=prec,
                         batch=(B.row_fold, B.inst_fold, B.inst_lambda)) as g:
         rep = g.autotune(target=1e-9, probe_epochs=6)
-        say(f"config5 autotune: step law c = {rep.step_groups:.0f}, cap = {rep.step_cap}, hot {rep.hot_columns}")
+        say(f"config5 {precision} autotune: step law c = {rep.step_groups:.0f}, cap = {rep.step_cap}, "
+            f"hot {rep.hot_columns}")
         active = np.ones(ni, dtype=np.uint8)
         rel = np.full(ni, np.inf)
         ep = 0
@@ -361,7 +368,7 @@ def test_batched_config5_all_160_reach_1e9(golden):
             g.set_active(active)
             if ep % 30 == 0:
                 say(f"config5 batched: {ep} epochs, {int(active.sum())} instances still active")
-        say(f"config5 batched: {ep} epochs, worst rel {np.max(rel):.2e}")
+        say(f"config5 batched {precision}: {ep} epochs, worst rel {np.max(rel):.2e}")
         assert np.all(rel <= 1e-9)
         assert np.all(rel >= -1e-11)
 
@@ -576,7 +583,8 @@ def test_batched_graph_replays_match_plain_launches():
         say(f"graph == plain over 5 calls; objectives {['%.6f' % f for f in fg]}")
 
 
-def test_batched_autotune_mixed_bf16_with_active_mask_reaches_1e9():
+@pytest.mark.parametrize("precision", ["mixed", "f32"])
+def test_batched_autotune_mixed_bf16_with_active_mask_reaches_1e9(precision):
     """The batched configuration of the lambda-path x folds workload, scaled
     down: bfloat16 values, FP32 x and alpha with FP64 abar, autotuned
     wavefronts per instance and step, instances switched off as they reach
@@ -592,7 +600,7 @@ def test_batched_autotune_mixed_bf16_with_active_mask_reaches_1e9():
         sub = datagen.subproblem(q, np.nonzero(B.row_fold != f)[0], lam=lam)
         fstars.append(oracle.certified_fstar(sub, tol=1e-12, check_every=10)["f_lower"])
     fstars = np.array(fstars)
-    with A.from_problem(q, bf16=True, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED,
+    with A.from_problem(q, bf16=True, mode=A.ASAGA_MODE_ASYNC, precision=PRECISIONS[precision],
                         batch=(B.row_fold, inst_fold, inst_lam)) as g:
         rep = g.autotune(target=1e-9, probe_epochs=6)
         say(f"batched autotune: {rep.candidates} candidates, waves/inst {rep.waves} hot {rep.hot_columns} "
@@ -607,30 +615,73 @@ def test_batched_autotune_mixed_bf16_with_active_mask_reaches_1e9():
             g.set_active(active)
             if not active.any():
                 break
-        say(f"batched mixed: {5 * (e + 1)} epochs, rel {['%.1e' % r for r in rels]}")
+        say(f"batched {precision}: {5 * (e + 1)} epochs, rel {['%.1e' % r for r in rels]}")
         assert np.all(rels <= 1e-9)
         assert np.all(rels >= -1e-11)   # never below the certified optimum (beyond rounding)
 
 
-def test_mixed_precision_reaches_1e9():
+@pytest.mark.parametrize("precision", ["mixed", "f32"])
+def test_mixed_precision_reaches_1e9(precision):
     p = datagen.config2(n=20_000, d=5000)
     r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
-    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED, waves=64) as g:
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, precision=PRECISIONS[precision], waves=64) as g:
         for e in range(60):
             g.epochs(5)
             rel = (g.objective() - r["f_lower"]) / r["f_lower"]
             if rel <= 1e-9:
                 break
-        say(f"mixed FP32 x/alpha, FP64 abar: {5 * (e + 1)} epochs, rel {rel:.2e}")
+        say(f"{precision}: FP32 x/alpha: {5 * (e + 1)} epochs, rel {rel:.2e}")
         assert rel <= 1e-9
         x, alpha, abar, t = g.get_state()
         # FP32 memory: alpha_i + delta rounds to FP32 whenever another wavefront
         # changed alpha_i between this sample's read and write (a few percent of
-        # updates on 20,000 rows), while abar receives delta in FP64; the
-        # running average therefore agrees to FP32 rounding, not FP64
+        # updates on 20,000 rows), while abar receives the change computed from
+        # the value read; the running average therefore agrees to FP32
+        # rounding, not FP64 (FP32 abar: also the rounding of its own sums)
         err = rel_err(abar, oracle.SparseSaga(p).memory_average(alpha))
-        say(f"mixed: abar vs (1/n) A^T alpha: {err:.1e}")
-        assert err < 1e-6
+        say(f"{precision}: abar vs (1/n) A^T alpha: {err:.1e}")
+        assert err < (1e-6 if precision == "mixed" else 1e-5)
+        if precision == "f32":
+            # re-anchoring recomputes it in FP64 and rounds once
+            g.reanchor()
+            x, alpha, abar, t = g.get_state()
+            assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 2.0 ** -23
+
+
+def test_f32_state_widens_to_fp64_and_polishes_to_1e9():
+    """FP32 x and abar, then asaga_widen: x is carried over exactly, abar is
+    recomputed from alpha in FP64, and FP64 epochs continue to 1e-9."""
+    p = datagen.config2(n=20_000, d=5000)
+    r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_F32, waves=64) as g:
+        g.epochs(10)
+        x32, _, _, t32 = g.get_state()
+        f32 = g.objective()
+        assert np.array_equal(x32, x32.astype(np.float32).astype(np.float64))
+        g.widen()
+        x, alpha, abar, t = g.get_state()
+        assert t == t32 and np.array_equal(x, x32) and g.objective() == f32
+        assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-12
+        ep, rel = run_to(g, r["f_lower"], max_epochs=200, every=5)
+        say(f"f32 then FP64: {ep} FP64 epochs after 10 FP32 ones, rel {rel:.2e}")
+        assert rel <= 1e-9
+        x, alpha, abar, t = g.get_state()
+        assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-11
+
+
+def test_f32_state_round_trip():
+    """asaga_set_state / asaga_get_state in the FP32 layout: values come back
+    rounded to FP32, in the caller's column order."""
+    p = datagen.config2(n=3000, d=1500)
+    rng = np.random.default_rng(4)
+    x, abar, alpha = rng.standard_normal(p.d), rng.standard_normal(p.d), rng.standard_normal(p.n)
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_F32) as g:
+        g.set_state(x=x, alpha=alpha, abar=abar, t=17)
+        gx, ga, gb, t = g.get_state()
+        r32 = lambda v: v.astype(np.float32).astype(np.float64)  # noqa: E731
+        assert t == 17
+        assert np.array_equal(gx, r32(x)) and np.array_equal(gb, r32(abar)) and np.array_equal(ga, r32(alpha))
+        assert g.objective() == pytest.approx(oracle.SparseSaga(p).objective(r32(x)), rel=1e-13)
 
 
 def compare_svrg_serial(p, epochs, seed=0, tol=1e-12):
