@@ -9,15 +9,21 @@ scalar gradient, scatter of x and abar, memory update).
 
 Prints one JSON line: updates/s, algorithmic HBM GB/s against the 8 TB/s
 roofline (per-launch time measured with HIP events on the library's
-stream), the time to 1e-9 relative suboptimality from a cold start, the
-batched leg (160 lambda x fold instances over the same matrix in bfloat16,
-mixed precision and again with FP64 state, to 1e-9 each, against the same
-instances solved one by one with the plain FP64 kernel), and the CPU oracle
-timed on a bounded sample on one pinned core of this host.
+stream) next to the measured memory-side request ceiling, the time to 1e-9
+relative suboptimality from a cold start, the overlap sweep (iterations to
+1e-9 against samples in flight at a fixed small step), atomic against racy
+updates (Appendix G), the batched leg (160 lambda x fold instances over the
+same matrix in bfloat16: FP32 state, mixed precision and FP64 state, to
+1e-9 each, against the same instances solved one by one with the plain FP64
+kernel), the other workloads (the tiny serial instance, the Covtype-shaped
+least squares in FP64 and FP32 then FP64, the URL-shaped instance in FP32
+state), and the CPU oracle timed on bounded samples of each workload on this
+host's cores, with its own time to 1e-9.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--skip-cpu] [--skip-tta]
                     [--skip-batched] [--no-batched-f64-state] [--plain-instances N]
-                    [--library-defaults] [--tau-sweep] [--copy-calibration]
+                    [--library-defaults] [--no-tau-sweep] [--skip-racy] [--skip-configs]
+                    [--copy-calibration]
 
 --copy-calibration adds a plain 1 GiB device-to-device copy (known bytes
 read and written) so that a profiler's per-dispatch byte counters can be
@@ -42,6 +48,11 @@ REQUEST_SUMMARY = os.path.join(ROOT, "profiles", "k_update_config2_requests.txt"
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def load_golden():
+    with open(os.path.join(ROOT, "tests", "golden", "fstar.json")) as fh:
+        return json.load(fh)
 
 
 def host_cpu_model():
@@ -150,13 +161,15 @@ def tau_sweep(p, dev_arrays, fstar, stream):
 def batched_leg(args, dev, stream):
     """The lambda path x folds workload (160 instances over the bfloat16
     config-2 matrix): all instances in one persistent kernel per epoch,
-    replayed from a captured hipGraph, mixed precision (FP32 x and alpha,
-    FP64 abar, bfloat16 values), autotuned wavefronts per instance and step;
-    each instance is switched off once it is within 1e-9 of its certified
-    optimum.  Then the same batch with FP64 state (still bfloat16 values),
-    and the same instances one by one with the plain FP64 async kernel.
-    Times are kernel times between HIP events; the objective checks between
-    them (after every epoch, in all three) are not counted."""
+    replayed from a captured hipGraph, autotuned wavefronts per instance,
+    hot-set size and step; each instance is switched off once it is within
+    1e-9 of its certified optimum.  Three state precisions: FP32 x, alpha
+    and abar in 8-byte slots (the headline), mixed (FP32 x and alpha, FP64
+    abar) and FP64; then the same instances one by one with the plain FP64
+    async kernel.  Kernel times are between HIP events; the objective checks
+    between them (after every launch) are not counted there, and the
+    end-to-end wall time of each batched solve, checks and re-planning
+    included, is reported beside it."""
     import numpy as np
     import torch
 
@@ -166,8 +179,7 @@ def batched_leg(args, dev, stream):
     t = time.time()
     B = datagen.config5()
     p = B.problem
-    with open(os.path.join(ROOT, "tests", "golden", "fstar.json")) as fh:
-        gold = json.load(fh).get("config5")
+    gold = load_golden().get("config5")
     if gold is None:
         raise SystemExit("tests/golden/fstar.json has no config5 entry")
     import hashlib
@@ -187,6 +199,10 @@ def batched_leg(args, dev, stream):
     torch.cuda.synchronize()
     m = np.array([int(np.sum(B.row_fold != f)) for f in B.inst_fold])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # algorithmic bytes per update: the row list entry (4), row bounds (16),
+    # label (8), bfloat16 values and int32 indices (6 per entry), memory read
+    # and write (2 x its size)
+    mean_k = p.nnz / p.n
 
     def run_batched(precision, label):
         g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
@@ -204,6 +220,8 @@ def batched_leg(args, dev, stream):
         # holding more workgroups than others applies more per launch)
         applied = np.zeros(ni, dtype=np.int64)
         kernel_s, launches, check = 0.0, 0, 1
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
         while active.any() and launches < 600:
             e0.record(stream)
             g.epochs(check)
@@ -217,25 +235,39 @@ def batched_leg(args, dev, stream):
                     active[k] = 0
                     applied[k] = g.instance(int(k)).t
             g.set_active(active)
-            log(f"batched {label}: {launches} launches, {int(active.sum())} instances still active, "
-                f"kernel {kernel_s:.3f} s")
+            if launches % 8 == 0 or not active.any():
+                log(f"batched {label}: {launches} launches, {int(active.sum())} instances still active, "
+                    f"kernel {kernel_s:.3f} s")
+        wall_s = time.perf_counter() - w0
         for k in np.nonzero(active)[0]:
             applied[k] = g.instance(int(k)).t
+        hot = g.info().hot_columns
         g.close()
         epochs = applied / m
         updates = int(applied.sum())
+        s_alpha = 8 if precision == A.ASAGA_PREC_F64 else 4
+        bpu = 4 + 16 + 8 + 6 * mean_k + 2 * s_alpha
+        gbps = bpu * updates / kernel_s / 1e9
         return {"instances": ni, "reached": int(np.sum(rel <= 1e-9)), "launches": launches,
                 "epochs_max": float(epochs.max()), "epochs_median": float(np.median(epochs)),
-                "seconds_to_1e-9_all": kernel_s, "updates": updates, "updates_per_s": updates / kernel_s,
-                "worst_rel_subopt": float(np.max(rel)), "autotune": tune}
+                "seconds_to_1e-9_all": kernel_s, "wall_seconds_to_1e-9_all": wall_s, "updates": updates,
+                "updates_per_s": updates / kernel_s, "worst_rel_subopt": float(np.max(rel)),
+                "hot_columns_last_launch": hot,
+                "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                             "frac": gbps / HBM_PEAK_GBPS, "bytes_per_update": bpu,
+                             "kernel": "k_update_batched"},
+                "autotune": tune}
 
     out = {"workload": "config5: 32 lambdas (1e-8..1e-2) x 5 uneven folds over the bfloat16 config-2 matrix, "
-                       "mixed precision (FP32 x/alpha, FP64 abar), one persistent kernel per epoch from a hipGraph"}
-    out.update(run_batched(A.ASAGA_PREC_MIXED, "mixed"))
-    log(f"batched: {out}")
+                       "FP32 x, alpha and abar (8-byte slots, compensated hot-column flushes), one persistent "
+                       "kernel per launch from a hipGraph"}
+    out.update(run_batched(A.ASAGA_PREC_F32, "FP32 state"))
+    log(f"batched FP32 state: {out}")
+    out["mixed"] = run_batched(A.ASAGA_PREC_MIXED, "mixed")
+    out["mixed"]["workload"] = "the same batch, FP32 x/alpha, FP64 abar, bfloat16 values"
+    log(f"batched mixed: {out['mixed']}")
     if args.batched_f64_state:
-        # the same batch with FP64 x and alpha (values still bfloat16): one
-        # atomic request per lane pair instead of two
+        # the same batch with FP64 x, alpha and abar (values still bfloat16)
         out["f64_state"] = run_batched(A.ASAGA_PREC_F64, "FP64 state")
         out["f64_state"]["workload"] = "the same batch, FP64 x/alpha/abar, bfloat16 values"
         log(f"batched FP64 state: {out['f64_state']}")
@@ -266,7 +298,8 @@ def batched_leg(args, dev, stream):
                 r = (g.objective() - fstar[k]) / fstar[k]
             plain_reached += int(r <= 1e-9)
             plain_epochs.append(ep)
-            log(f"plain instance {k}: {ep} epochs, rel {r:.2e}, total kernel {plain_s:.3f} s")
+            if k % 16 == 15:
+                log(f"plain instance {k}: {ep} epochs, rel {r:.2e}, total kernel {plain_s:.3f} s")
             g.close()
         del arrs
     scale = ni / len(sel)
@@ -280,6 +313,396 @@ def batched_leg(args, dev, stream):
     return out
 
 
+def batched_throughput(args, dev, stream, precisions=None):
+    """Kernel throughput of the batched update with all 160 instances of the
+    config-5 batch active: `warmup` launches, then `steps` launches in one
+    asaga_epochs call (replayed from its captured hipGraph), at the default
+    step law and automatic workgroups (what asaga_autotune chooses on this
+    batch); updates/s from the instances' sample counters and HIP events
+    on the library's stream, and the algorithmic HBM rate."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    B = datagen.config5()
+    p = B.problem
+    arrs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+            for a in (p.rowptr, p.colidx, p.val_bf16.view(np.int16), p.b)]
+    torch.cuda.synchronize()
+    mean_k = p.nnz / p.n
+    out = {}
+    names = {A.ASAGA_PREC_F32: "f32_state", A.ASAGA_PREC_MIXED: "mixed", A.ASAGA_PREC_F64: "f64_state"}
+    for prec in precisions or (A.ASAGA_PREC_F32, A.ASAGA_PREC_F64):
+        g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
+                     precision=prec, stream=stream, batch=(B.row_fold, B.inst_fold, B.inst_lambda))
+        g.epochs(args.warmup)
+        torch.cuda.synchronize()
+        t0 = sum(g.instance(k).t for k in range(B.n_inst))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.epochs(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        updates = sum(g.instance(k).t for k in range(B.n_inst)) - t0
+        info = g.info()
+        g.close()
+        bpu = 4 + 16 + 8 + 6 * mean_k + 2 * (8 if prec == A.ASAGA_PREC_F64 else 4)
+        gbps = bpu * updates / (ms / 1e3) / 1e9
+        out[names[prec]] = {"launches": args.steps, "ms_per_launch": ms / args.steps, "updates": int(updates),
+                            "updates_per_s": updates / (ms / 1e3), "hot_columns": info.hot_columns,
+                            "threads_per_block": info.threads_per_block, "bytes_per_update": bpu,
+                            "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                         "frac": gbps / HBM_PEAK_GBPS, "kernel": "k_update_batched"}}
+        log(f"batched throughput {names[prec]}: {out[names[prec]]}")
+    return out
+
+
+def config4_throughput(args, dev, stream, p=None):
+    """Kernel throughput of the URL-shaped instance (bfloat16 values, FP32
+    state) at a fixed launch shape: `warmup` epochs, then `steps` timed."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    p = datagen.config4() if p is None else p
+    arrs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+            (p.rowptr, p.colidx, p.val_bf16.view(np.int16), p.b)]
+    torch.cuda.synchronize()
+    g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
+                 precision=A.ASAGA_PREC_F32, waves=args.config4_waves, stream=stream)
+    g.epochs(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.epochs(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    info = g.info()
+    g.close()
+    bpu = 6 * p.nnz / p.n + 16 + 8 + 8
+    gbps = bpu * p.n / (ms / 1e3) / 1e9
+    out = {"waves": info.waves, "threads_per_block": info.threads_per_block, "hot_columns": info.hot_columns,
+           "ms_per_epoch": ms, "updates_per_s": p.n / (ms / 1e3), "bytes_per_update": bpu,
+           "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": gbps / HBM_PEAK_GBPS, "kernel": "k_update (FP32 state, bfloat16 values)"}}
+    log(f"config4 throughput: {out}")
+    return out
+
+
+def racy_leg(dev, stream):
+    """Appendix G: the same instance, step and launch with atomic additions
+    and with plain read-modify-writes (no LDS combining, so every write of
+    the racy run goes to the shared state unprotected): relative
+    suboptimality after 10, 20, 40 and 60 epochs."""
+    import numpy as np
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    p = datagen.config2(n=20_000, d=2000)
+    gold = load_golden()["config2_20000x2000"]
+    if gold["digest"] != p.digest():
+        raise SystemExit("the 20,000-row instance differs from the one its optimum was computed on")
+    fstar = gold["f_lower"]
+    rule = 1.0 / (3.0 * (0.25 * float(np.max(np.add.reduceat(p.val ** 2, p.rowptr[:-1]))) + p.lam))
+    out = {"workload": "RCV1-shaped recipe at 20,000 x 2,000, lambda = 1/n, 512 wavefronts, no hot set, "
+                       "step = serial rule / 4, 60 epochs", "target": 1e-9}
+    for racy in (0, 1):
+        g = A.Solver(p.n, p.d, p.rowptr, p.colidx, p.val, p.b, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC,
+                     waves=512, racy=racy, hot_columns=-1, step=rule / 4, stream=stream)
+        rels = []
+        for e in range(60):
+            g.epochs(1)
+            try:
+                rels.append((g.objective() - fstar) / fstar)
+            except A.AsagaError:
+                rels.append(float("inf"))
+        g.close()
+        key = "racy" if racy else "atomic"
+        out[key] = {"rel_subopt_at_epochs": {str(e): rels[e - 1] for e in (10, 20, 40, 60)},
+                    "best_rel_subopt": min(rels), "reached_target": min(rels) <= 1e-9}
+        log(f"{key}: {out[key]}")
+    return out
+
+
+def config1_leg(stream):
+    """The tiny instance in the deterministic serial mode (one lane group in
+    the oracle's sample order), 50 epochs, each timed; relative
+    suboptimality against the Newton optimum after each."""
+    import torch
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    p = datagen.config1()
+    gold = load_golden()["config1"]
+    if gold["digest"] != p.digest():
+        raise SystemExit("config1 differs from the instance f* was computed on")
+    fstar = gold["f_star"]
+    g = A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    secs, first, rel = 0.0, None, float("inf")
+    for e in range(1, 51):
+        e0.record(stream)
+        g.epochs(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        secs += e0.elapsed_time(e1) / 1e3
+        rel = (g.objective() - fstar) / fstar
+        if first is None and rel <= 1e-9:
+            first = (e, secs)
+    g.close()
+    return {"workload": "config1: 2,000 x 500 L2 logistic, serial FP64 (one lane group, oracle sample order)",
+            "epochs": 50, "seconds": secs, "updates_per_s": 50 * p.n / secs, "rel_subopt_after_50": rel,
+            "epochs_to_1e-9": first[0] if first else None, "seconds_to_1e-9": first[1] if first else None}
+
+
+def run_until(g, fstar, stream, target=1e-9, max_epochs=800, every=5):
+    """Kernel seconds (HIP events) and epochs until (f - f*)/f* <= target."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    secs, ep, rel = 0.0, 0, float("inf")
+    while ep < max_epochs and rel > target:
+        e0.record(stream)
+        g.epochs(every)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        secs += e0.elapsed_time(e1) / 1e3
+        ep += every
+        rel = (g.objective() - fstar) / fstar
+    return ep, secs, rel
+
+
+def config3_leg(dev, stream):
+    """The Covtype-shaped least squares (581,000 x 54, the same ten dense
+    columns in every row): FP64 async, autotuned; then FP32 state (100
+    epochs, where FP32 x stalls near 1e-7), widened to FP64 and polished to
+    1e-9."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    p = datagen.config3()
+    gold = load_golden()["config3"]
+    if gold["digest"] != p.digest():
+        raise SystemExit("config3 differs from the instance f* was computed on")
+    fstar = gold["f_star"]
+    arrs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (p.rowptr, p.colidx, p.val, p.b)]
+    torch.cuda.synchronize()
+    out = {"workload": "config3: 581,000 x 54 L2 least squares, lambda = 1e-4 (FP64 values)"}
+    bpu = 12 * p.nnz / p.n + 16 + 8 + 16
+    g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC, stream=stream)
+    t = time.time()
+    rep = g.autotune(target=1e-9, probe_epochs=9)
+    tune_s = time.time() - t
+    ep, secs, rel = run_until(g, fstar, stream)
+    out["fp64"] = {"epochs": ep, "seconds_to_1e-9": secs, "final_rel_subopt": rel, "reached": rel <= 1e-9,
+                   "updates_per_s": ep * p.n / secs, "hbm_gbps_algorithmic": bpu * ep * p.n / secs / 1e9,
+                   "waves": rep.waves, "gamma_over_serial_rule": rep.gamma * 3.0 * g.info().L,
+                   "autotune_wall_s": tune_s}
+    g.close()
+    log(f"config3 FP64: {out['fp64']}")
+    g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_F32,
+                 stream=stream)
+    rep = g.autotune(target=1e-9, probe_epochs=9)
+    ep32, s32, rel32 = run_until(g, fstar, stream, max_epochs=100, every=10)
+    g.widen()
+    ep64, s64, rel64 = run_until(g, fstar, stream, every=10)
+    out["fp32_then_fp64"] = {"fp32_epochs": ep32, "fp32_seconds": s32, "rel_subopt_fp32": rel32,
+                             "fp64_epochs": ep64, "fp64_seconds": s64, "final_rel_subopt": rel64,
+                             "reached": rel64 <= 1e-9, "seconds_to_1e-9": s32 + s64,
+                             "fp32_updates_per_s": ep32 * p.n / s32 if s32 > 0 else None}
+    g.close()
+    log(f"config3 FP32 then FP64: {out['fp32_then_fp64']}")
+    return out
+
+
+def config4_leg(dev, stream, p=None):
+    """The URL-shaped instance (2.4M x 3.2M, ~115 binary entries per row,
+    bfloat16 values): FP32 state, autotuned shape and step, to 1e-9."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1606_04809_amd as A
+
+    t = time.time()
+    p = datagen.config4() if p is None else p
+    gold = load_golden()["config4"]
+    if gold["digest"] != p.digest():
+        raise SystemExit("config4 differs from the instance f* was computed on")
+    log(f"generated config4 in {time.time() - t:.1f}s")
+    fstar = gold["f_lower"]
+    arrs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
+            (p.rowptr, p.colidx, p.val_bf16.view(np.int16), p.b)]
+    torch.cuda.synchronize()
+    g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
+                 precision=A.ASAGA_PREC_F32, stream=stream)
+    t = time.time()
+    log("config4: autotune probing wavefronts and step")
+    rep = g.autotune(target=1e-9, probe_epochs=6)
+    tune_s = time.time() - t
+    log(f"config4 autotune: waves {rep.waves}, gamma {rep.gamma:.4g}, {rep.ms_per_epoch:.1f} ms/epoch, "
+        f"{tune_s:.1f} s")
+    ep, secs, rel = run_until(g, fstar, stream, max_epochs=400)
+    info = g.info()
+    g.close()
+    bpu = 6 * p.nnz / p.n + 16 + 8 + 8
+    out = {"workload": "config4: 2,400,000 x 3,200,000 L2 logistic, bfloat16 values, FP32 state",
+           "epochs": ep, "seconds_to_1e-9": secs, "final_rel_subopt": rel, "reached": rel <= 1e-9,
+           "updates_per_s": ep * p.n / secs, "hbm_gbps_algorithmic": bpu * ep * p.n / secs / 1e9,
+           "hbm_frac": bpu * ep * p.n / secs / 1e9 / HBM_PEAK_GBPS, "bytes_per_update": bpu,
+           "waves": info.waves, "threads_per_block": info.threads_per_block, "hot_columns": info.hot_columns,
+           "gamma": info.gamma, "gamma_over_serial_rule": info.gamma * 3.0 * info.L, "autotune_wall_s": tune_s}
+    log(f"config4: {out}")
+    return out
+
+
+def cpu_legs(args, p2, p4):
+    """The CPU oracle (single-thread FP64 Sparse SAGA, the test
+    infrastructure's reference) timed on bounded samples of each workload on
+    this host, after the GPU work.  Config 2 (the headline): epochs on one
+    pinned core.  The oracle's time to 1e-9 is its stored epochs to 1e-9
+    (written by tests/golden/make_golden.py) times the seconds per epoch
+    measured here, except on config 1, which runs to 1e-9 here.  Config 5:
+    one instance per thread on up to 16 host cores at once (the oracle's C
+    loop runs outside the interpreter lock), one epoch each; the time for
+    all 160 instances is their stored epochs times the per-epoch times
+    measured under that load, packed perfectly onto those cores."""
+    import dataclasses
+    import threading
+
+    import numpy as np
+
+    import datagen
+    import oracle
+
+    gold = load_golden()
+    out = {}
+    prev, core = None, None
+    try:
+        prev = os.sched_getaffinity(0)
+        core = min(prev)
+        os.sched_setaffinity(0, {core})
+    except (AttributeError, OSError):
+        prev = None
+    try:
+        sv = oracle.SparseSaga(p2, seed=0)
+        t = time.perf_counter()
+        sv.epochs(args.cpu_epochs)
+        dt = time.perf_counter() - t
+        tta2 = gold["config2"]["oracle_tta"]["epochs"]
+        out["config2"] = {"value": args.cpu_epochs * p2.n / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                          "sample": f"{args.cpu_epochs} epochs ({args.cpu_epochs * p2.n} updates) of the config-2 "
+                                    f"workload, serial FP64 Sparse SAGA, one thread pinned to one core, {dt:.1f} s",
+                          "pinned_core": core, "seconds_per_epoch": dt / args.cpu_epochs,
+                          "epochs_to_1e-9": tta2, "seconds_to_1e-9_est": tta2 * dt / args.cpu_epochs}
+        log(f"cpu oracle config2: {out['config2']}")
+        # config 1: to 1e-9 here, checks not timed
+        p1 = datagen.config1()
+        f1 = gold["config1"]["f_star"]
+        sv = oracle.SparseSaga(p1)
+        secs, ep, rel = 0.0, 0, float("inf")
+        while rel > 1e-9 and ep < 200:
+            t = time.perf_counter()
+            sv.epochs(1)
+            secs += time.perf_counter() - t
+            ep += 1
+            rel = (sv.objective() - f1) / f1
+        out["config1"] = {"epochs_to_1e-9": ep, "seconds_to_1e-9": secs, "updates_per_s": ep * p1.n / secs,
+                          "cores": 1}
+        # config 3 and 4: bounded samples
+        p3 = datagen.config3()
+        sv = oracle.SparseSaga(p3)
+        t = time.perf_counter()
+        sv.epochs(3)
+        dt = time.perf_counter() - t
+        e3 = gold["config3"]["oracle_tta"]["epochs"]
+        out["config3"] = {"updates_per_s": 3 * p3.n / dt, "seconds_per_epoch": dt / 3, "epochs_to_1e-9": e3,
+                          "seconds_to_1e-9_est": e3 * dt / 3, "cores": 1, "sample": "3 epochs"}
+        if p4 is not None:
+            sv = oracle.SparseSaga(p4)
+            t = time.perf_counter()
+            sv.epochs(1)
+            dt = time.perf_counter() - t
+            e4 = gold["config4"]["oracle_tta"]["epochs"]
+            out["config4"] = {"updates_per_s": p4.n / dt, "seconds_per_epoch": dt, "epochs_to_1e-9": e4,
+                              "seconds_to_1e-9_est": e4 * dt, "cores": 1, "sample": "1 epoch"}
+            del sv
+        log(f"cpu oracle configs 1, 3, 4: {out.get('config1')}, {out.get('config3')}, {out.get('config4')}")
+    finally:
+        if prev is not None:
+            os.sched_setaffinity(0, prev)
+
+    # config 5: one instance per thread on up to 16 cores
+    cores = sorted(prev) if prev is not None else list(range(os.cpu_count() or 1))
+    P = max(1, min(16, len(cores)))
+    B = datagen.config5()
+    g5 = {e["k"]: e for e in gold["config5"]["instances"]}
+    by_fold = {}
+    for f in range(5):
+        k = int(np.nonzero(B.inst_fold == f)[0][0])
+        by_fold[f] = B.instance(k)
+    ks = np.unique(np.linspace(0, B.n_inst - 1, P).round().astype(int))
+    solvers = [oracle.SparseSaga(dataclasses.replace(by_fold[int(B.inst_fold[k])], lam=float(B.inst_lambda[k])))
+               for k in ks]
+    barrier = threading.Barrier(len(ks))
+    secs = [0.0] * len(ks)
+
+    def work(j):
+        try:
+            os.sched_setaffinity(0, {cores[j % len(cores)]})
+        except (AttributeError, OSError):
+            pass
+        barrier.wait()
+        t = time.perf_counter()
+        solvers[j].epochs(1)
+        secs[j] = time.perf_counter() - t
+
+    t = time.perf_counter()
+    threads = [threading.Thread(target=work, args=(j,)) for j in range(len(ks))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    wall = time.perf_counter() - t
+    if prev is not None:
+        os.sched_setaffinity(0, prev)
+    per_update = float(np.mean([secs[j] / solvers[j].n for j in range(len(ks))]))
+    core_s = sum(g5[k]["oracle_tta"]["epochs"] * g5[k]["m"] * per_update for k in range(B.n_inst))
+    m_run = sum(solvers[j].n for j in range(len(ks)))
+    out["config5"] = {"cores": len(ks), "updates_per_s": m_run / wall,
+                      "sample": f"one epoch each of {len(ks)} instances (spread over lambda and folds), one per "
+                                f"thread, {wall:.1f} s",
+                      "epochs_to_1e-9_median": float(np.median([g5[k]["oracle_tta"]["epochs"] for k in g5])),
+                      "epochs_to_1e-9_max": int(max(g5[k]["oracle_tta"]["epochs"] for k in g5)),
+                      "seconds_to_1e-9_all_160_est": core_s / len(ks)}
+    log(f"cpu oracle config5: {out['config5']}")
+    return out
+
+
+def copy_calibration(dev):
+    """A plain 1 GiB device-to-device copy (known bytes read and written), so
+    that a profiler's per-dispatch byte counters can be scaled to bytes."""
+    import torch
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {src.numel() * 8} bytes read and written")
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +712,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--skip-cpu", action="store_true", help="omit the CPU oracle leg")
     ap.add_argument("--skip-tta", action="store_true", help="omit the time-to-accuracy leg")
-    ap.add_argument("--cpu-epochs", type=int, default=50)
+    ap.add_argument("--cpu-epochs", type=int, default=30)
     ap.add_argument("--hot", type=int, default=0)
     ap.add_argument("--flush", type=int, default=0)
     # The benchmarked shape: 1024-thread workgroups, one per compute unit
@@ -306,11 +729,19 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library's default launch shape and step instead of asaga_autotune's choice")
     ap.add_argument("--skip-batched", action="store_true", help="omit the batched lambda-path x folds leg")
-    ap.add_argument("--tau-sweep", action="store_true",
-                    help="add the overlap sweep: samples in flight (measured) and epochs to 1e-9 at a fixed step "
-                         "versus wavefronts in flight")
+    ap.add_argument("--no-tau-sweep", dest="tau_sweep", action="store_false",
+                    help="omit the overlap sweep (samples in flight, measured, and epochs to 1e-9 at a fixed step "
+                         "versus wavefronts in flight)")
+    ap.add_argument("--skip-racy", action="store_true", help="omit the atomic vs racy comparison (Appendix G)")
+    ap.add_argument("--skip-configs", action="store_true",
+                    help="omit the legs of the other workloads (tiny serial, Covtype-shaped, URL-shaped)")
     ap.add_argument("--no-batched-f64-state", dest="batched_f64_state", action="store_false",
                     help="omit the batched run with FP64 state (the mixed-precision batched run stays)")
+    ap.add_argument("--only", choices=("config2", "batched", "config4"), default=None,
+                    help="run only that workload's throughput measurement (for profiling runs): config2 at the "
+                         "benchmarked shape, the config-5 batch with every instance active, or config4 at "
+                         "--config4-waves wavefronts; --steps and --warmup apply")
+    ap.add_argument("--config4-waves", type=int, default=512)
     ap.add_argument("--plain-instances", type=int, default=160,
                     help="instances of the batch also solved one by one with the plain FP64 kernel (spread "
                          "evenly over the 160)")
@@ -332,11 +763,26 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
+    if args.only in ("batched", "config4"):
+        if args.copy_calibration:
+            copy_calibration(dev)
+        if args.only == "batched":
+            res = batched_throughput(args, dev, stream,
+                                     (A.ASAGA_PREC_F32, A.ASAGA_PREC_MIXED, A.ASAGA_PREC_F64))
+        else:
+            res = config4_throughput(args, dev, stream)
+        print(json.dumps({"only": args.only, "steps": args.steps, "warmup": args.warmup, "result": res}),
+              flush=True)
+        return
+    if args.only == "config2":
+        args.no_autotune = args.skip_tta = args.skip_batched = args.skip_racy = True
+        args.skip_configs = args.skip_cpu = True
+        args.tau_sweep = False
+
     t = time.time()
     p = datagen.config2()
     log(f"generated config2 n={p.n} d={p.d} nnz={p.nnz} in {time.time() - t:.1f}s")
-    with open(os.path.join(ROOT, "tests", "golden", "fstar.json")) as fh:
-        gold = json.load(fh)["config2"]
+    gold = load_golden()["config2"]
     if gold["digest"] != p.digest():
         raise SystemExit("config2 instance differs from the one f* was computed on")
     fstar = gold["f_lower"]
@@ -378,14 +824,7 @@ def main():
         tta_shape.update(waves=rep.waves, hot_columns=rep.hot_columns, hot_tier_columns=rep.hot_tier_columns)
 
     if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"copy calibration: {src.numel() * 8} bytes read and written")
-        del src, dst
+        copy_calibration(dev)
 
     # ---- throughput: W warm-up epochs, then K timed epochs -------------------
     g = make_solver()
@@ -438,8 +877,12 @@ def main():
     if requests is not None:
         # memory-side requests per second at this run's measured update rate
         total = (requests["atomic_per_update"] + requests["read_per_update"]) * ups
+        per_update = requests["atomic_per_update"] + requests["read_per_update"]
         requests.update(atomic_per_s=requests["atomic_per_update"] * ups, read_per_s=requests["read_per_update"] * ups,
-                        frac_of_ceiling=total / ceil_mixed, source=os.path.relpath(REQUEST_SUMMARY, ROOT))
+                        frac_of_ceiling=total / ceil_mixed, source=os.path.relpath(REQUEST_SUMMARY, ROOT),
+                        # the request roofline: updates/s at which this many
+                        # memory-side requests per update meet the ceiling
+                        roofline_updates_per_s=ceil_mixed / per_update)
         log(f"memory-side requests: {total:.3e}/s = {total / ceil_mixed:.2f} of the ceiling")
 
     # ---- time to 1e-9 relative suboptimality from a cold start ----------------
@@ -476,35 +919,37 @@ def main():
             tta_tuned = time_to_target(tta_step, tta_shape)
             log(f"time to 1e-9 (autotuned shape): {tta_tuned}")
 
-    sweep = tau_sweep(p, dev_arrays, fstar, stream) if args.tau_sweep else None
+    sweep = None
+    if args.tau_sweep:
+        log("overlap sweep: 64 to 2048 wavefronts at 1/16 of the serial step")
+        sweep = tau_sweep(p, dev_arrays, fstar, stream)
     del dev_arrays
-    batched = None if args.skip_batched else batched_leg(args, dev, stream)
+    racy = None if args.skip_racy else racy_leg(dev, stream)
+    batched = None
+    if not args.skip_batched:
+        batched = batched_leg(args, dev, stream)
+        # kernel throughput with every instance active (3 launches after 1)
+        batched["throughput_all_active"] = batched_throughput(argparse.Namespace(steps=3, warmup=1), dev, stream)
+    others, p4 = None, None
+    if not args.skip_configs:
+        others = {"config1": config1_leg(stream)}
+        log(f"config1: {others['config1']}")
+        others["config3"] = config3_leg(dev, stream)
+        import datagen as _dg
+        t = time.time()
+        p4 = _dg.config4()
+        log(f"generated config4 n={p4.n} d={p4.d} nnz={p4.nnz} in {time.time() - t:.1f}s")
+        others["config4"] = config4_leg(dev, stream, p4)
+        torch.cuda.empty_cache()
 
-    # ---- CPU oracle on a bounded sample ------------------------------------------
+    # ---- CPU oracle on bounded samples -------------------------------------------
     cpu = None
     if not args.skip_cpu:
-        import oracle
-        sv = oracle.SparseSaga(p, seed=0)
-        # one thread pinned to one host core (the GPU work is done by now)
-        prev, core = None, None
-        try:
-            prev = os.sched_getaffinity(0)
-            core = min(prev)
-            os.sched_setaffinity(0, {core})
-        except (AttributeError, OSError):
-            prev = None
-        try:
-            t = time.perf_counter()
-            sv.epochs(args.cpu_epochs)
-            dt = time.perf_counter() - t
-        finally:
-            if prev is not None:
-                os.sched_setaffinity(0, prev)
-        cpu = {"value": args.cpu_epochs * p.n / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_epochs} epochs ({args.cpu_epochs * p.n} updates) of the same workload, "
-                         f"serial FP64 Sparse SAGA, one thread, {dt:.1f} s; host has {os.cpu_count()} cpus",
-               "pinned_core": core, "host_cpu": host_cpu_model()}
-        log(f"cpu oracle: {cpu}")
+        legs = cpu_legs(args, p, p4)
+        cpu = dict(legs["config2"])
+        cpu["host_cpu"] = host_cpu_model()
+        cpu["host_cpus"] = os.cpu_count()
+        cpu["other_workloads"] = {k: v for k, v in legs.items() if k != "config2"}
 
     out = {
         "metric": METRIC,
@@ -541,6 +986,8 @@ def main():
         "autotune": tune,
         "batched": batched,
         "tau_sweep": sweep,
+        "atomic_vs_racy": racy,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -11,6 +11,9 @@ computed by the CPU oracle only (never by the HIP library).
   until the strong-convexity certificate ||grad f||^2/(2 lambda) <= 1e-12 f
   holds; f* lies in [f_lower, f_upper].
 
+* config2_20000x2000 (the RCV1-shaped recipe at 20,000 x 2,000): the same
+  certificate, for the benchmark's comparison of atomic and racy updates.
+
 * config5 (160 lambda x fold instances over the bfloat16 config-2 matrix):
   the same certificate per instance, to 1e-11, one instance per worker
   process.
@@ -158,6 +161,11 @@ def add_tta(names, workers):
         json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
 
 
+# scaled-down RCV1-shaped instances the benchmark also runs (the Appendix G
+# comparison of atomic and racy updates)
+SCALED = {"config2_20000x2000": lambda: datagen.config2(n=20_000, d=2000)}
+
+
 def main(names):
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name in names:
@@ -170,7 +178,7 @@ def main(names):
             data[name] = e
             json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)
             continue
-        p = datagen.by_name(name)
+        p = SCALED[name]() if name in SCALED else datagen.by_name(name)
         print(f"{name}: generated n={p.n} d={p.d} nnz={p.nnz} in {time.time() - t:.1f}s", flush=True)
         if name == "config1":
             e = entry_newton(p)
