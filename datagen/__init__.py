@@ -168,19 +168,25 @@ def config1(seed: int = 0, n: int = 2000, d: int = 500, k: int = 25) -> Problem:
 
 
 def config2(seed: int = 0, n: int = 700_000, d: int = 47_000, mean_nnz: float = 75.0,
-            zipf_s: float = 1.1) -> Problem:
+            zipf_s: float = 1.1, idf: bool = True) -> Problem:
     """RCV1-like logistic instance (see module docstring).  Frequent columns
-    get small weights, as term weighting does in text data."""
+    get small weights, as term weighting does in text data.  idf=False
+    gives the other reading of the values: lognormal(0, 1) alone, then
+    row-normalised (the same supports)."""
     counts = np.maximum(1, _rng(seed, _T_COUNTS).poisson(mean_nnz, size=n))
     perm = _rng(seed, _T_PERM).permutation(d).astype(np.int32)
     rowptr, colidx = _distinct_supports(seed, n, d, counts, _zipf_cdf(d, zipf_s), perm)
     tf = _rng(seed, _T_VALUES).lognormal(0.0, 1.0, size=len(colidx))
-    df = np.bincount(colidx, minlength=d)
-    idf = np.log((1.0 + n) / (1.0 + df)) + 1.0
-    val = _row_normalise(rowptr, tf * idf[colidx])
+    if idf:
+        df = np.bincount(colidx, minlength=d)
+        w = np.log((1.0 + n) / (1.0 + df)) + 1.0
+        val = _row_normalise(rowptr, tf * w[colidx])
+    else:
+        val = _row_normalise(rowptr, tf)
     b = _planted_labels(seed, rowptr, colidx, val, d, 0.10)
     return Problem("config2", n, d, rowptr, colidx, val, b, LOGISTIC, 1.0 / n,
-                   meta={"zipf_s": zipf_s, "mean_nnz": mean_nnz, "values": "lognormal tf x smooth idf"})
+                   meta={"zipf_s": zipf_s, "mean_nnz": mean_nnz,
+                         "values": "lognormal tf x smooth idf" if idf else "lognormal"})
 
 
 def config3(seed: int = 0, n: int = 581_000, lam: float = 1e-4) -> Problem:

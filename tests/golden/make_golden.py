@@ -13,6 +13,8 @@ computed by the CPU oracle only (never by the HIP library).
 
 * config2_20000x2000 (the RCV1-shaped recipe at 20,000 x 2,000): the same
   certificate, for the benchmark's comparison of atomic and racy updates.
+* config2_plain_lognormal (config 2 with lognormal values and no idf
+  factor, the other reading of its values): the same certificate.
 
 * config5 (160 lambda x fold instances over the bfloat16 config-2 matrix):
   the same certificate per instance, to 1e-11, one instance per worker
@@ -152,7 +154,7 @@ def add_tta(names, workers):
             for e in data[name]["instances"]:
                 e["oracle_tta"] = res[e["k"]]
         else:
-            p = datagen.by_name(name)
+            p = SCALED[name]() if name in SCALED else datagen.by_name(name)
             if data[name]["digest"] != p.digest():
                 raise SystemExit(f"{name} differs from the stored instance")
             data[name]["oracle_tta"] = oracle_epochs_to(p, data[name]["f_lower"])
@@ -163,7 +165,8 @@ def add_tta(names, workers):
 
 # scaled-down RCV1-shaped instances the benchmark also runs (the Appendix G
 # comparison of atomic and racy updates)
-SCALED = {"config2_20000x2000": lambda: datagen.config2(n=20_000, d=2000)}
+SCALED = {"config2_20000x2000": lambda: datagen.config2(n=20_000, d=2000),
+          "config2_plain_lognormal": lambda: datagen.config2(idf=False)}
 
 
 def main(names):
