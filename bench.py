@@ -566,7 +566,10 @@ def config3_leg(dev, stream):
 
 def config4_leg(dev, stream, p=None):
     """The URL-shaped instance (2.4M x 3.2M, ~115 binary entries per row,
-    bfloat16 values): FP32 state, autotuned shape and step, to 1e-9."""
+    bfloat16 values): FP32 state, autotuned shape and step, to 1e-9; if the
+    FP32 iterate stalls above it (FP32 x cannot hold this optimum more
+    closely than its own rounding, which small steps raise), asaga_widen
+    switches to FP64 and the same shape polishes to 1e-9."""
     import numpy as np
     import torch
 
@@ -578,7 +581,7 @@ def config4_leg(dev, stream, p=None):
     gold = load_golden()["config4"]
     if gold["digest"] != p.digest():
         raise SystemExit("config4 differs from the instance f* was computed on")
-    log(f"generated config4 in {time.time() - t:.1f}s")
+    log(f"config4 ready in {time.time() - t:.1f}s")
     fstar = gold["f_lower"]
     arrs = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in
             (p.rowptr, p.colidx, p.val_bf16.view(np.int16), p.b)]
@@ -586,24 +589,43 @@ def config4_leg(dev, stream, p=None):
     g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
                  precision=A.ASAGA_PREC_F32, stream=stream)
     t = time.time()
-    log("config4: autotune probing wavefronts and step")
+    log("config4: autotune probing wavefronts and step, then racing the finalists")
     rep = g.autotune(target=1e-9, probe_epochs=6)
     tune_s = time.time() - t
-    log(f"config4 autotune: waves {rep.waves}, gamma {rep.gamma:.4g}, {rep.ms_per_epoch:.1f} ms/epoch, "
-        f"{tune_s:.1f} s")
-    ep, secs, rel = run_until(g, fstar, stream, max_epochs=400)
     info = g.info()
+    log(f"config4 autotune: waves {rep.waves}, gamma {rep.gamma:.4g}, {rep.ms_per_epoch:.1f} ms/epoch, "
+        f"{rep.est_epochs:.0f} epochs in the race, {tune_s:.1f} s")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # FP32 epochs until 1e-9, or until the FP32 iterate stalls: less than a
+    # 20% lower objective gap in the last 20 epochs
+    secs32, ep32, rel, hist = 0.0, 0, float("inf"), []
+    while ep32 < 400 and rel > 1e-9 and not (len(hist) > 4 and min(hist[-4:]) > 0.8 * min(hist[:-4])):
+        e0.record(stream)
+        g.epochs(5)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        secs32 += e0.elapsed_time(e1) / 1e3
+        ep32 += 5
+        rel = (g.objective() - fstar) / fstar
+        hist.append(rel)
+    rel32, secs64, ep64 = rel, 0.0, 0
+    if rel > 1e-9:
+        g.widen()
+        ep64, secs64, rel = run_until(g, fstar, stream, max_epochs=400)
     g.close()
+    ep, secs = ep32 + ep64, secs32 + secs64
     bpu = 6 * p.nnz / p.n + 16 + 8 + 8
-    out = {"workload": "config4: 2,400,000 x 3,200,000 L2 logistic, bfloat16 values, FP32 state",
+    out = {"workload": "config4: 2,400,000 x 3,200,000 L2 logistic, bfloat16 values, FP32 state (FP64 polish "
+                       "if FP32 stalls above the target)",
            "epochs": ep, "seconds_to_1e-9": secs, "final_rel_subopt": rel, "reached": rel <= 1e-9,
-           "updates_per_s": ep * p.n / secs, "hbm_gbps_algorithmic": bpu * ep * p.n / secs / 1e9,
-           "hbm_frac": bpu * ep * p.n / secs / 1e9 / HBM_PEAK_GBPS, "bytes_per_update": bpu,
-           "waves": info.waves, "threads_per_block": info.threads_per_block, "hot_columns": info.hot_columns,
-           "gamma": info.gamma, "gamma_over_serial_rule": info.gamma * 3.0 * info.L, "autotune_wall_s": tune_s}
+           "fp32_epochs": ep32, "fp32_seconds": secs32, "rel_subopt_fp32": rel32, "fp64_polish_epochs": ep64,
+           "fp64_polish_seconds": secs64, "fp32_updates_per_s": ep32 * p.n / secs32 if secs32 > 0 else None,
+           "fp32_hbm_gbps_algorithmic": bpu * ep32 * p.n / secs32 / 1e9 if secs32 > 0 else None,
+           "bytes_per_update_fp32": bpu, "waves": info.waves, "threads_per_block": info.threads_per_block,
+           "hot_columns": info.hot_columns, "gamma": info.gamma, "gamma_over_serial_rule": info.gamma * 3.0 * info.L,
+           "autotune_wall_s": tune_s, "autotune_race_epochs": rep.est_epochs}
     log(f"config4: {out}")
     return out
-
 
 def cpu_legs(args, p2, p4):
     """The CPU oracle (single-thread FP64 Sparse SAGA, the test

@@ -415,12 +415,13 @@ int asaga_set_state(asaga_ctx* ctx, int32_t inst, const double* x_host, const do
  * leave in the running average (every instance). */
 int asaga_reanchor(asaga_ctx* ctx);
 
-/* Mixed-precision contexts: widen every instance's state to FP64 (x in
- * place, alpha into a new FP64 array), recompute abar from alpha as
- * asaga_reanchor does, and continue in FP64 from there: the final polish,
- * since FP32 x cannot hold the optimum more closely than its own rounding
- * (and FP32 atomic additions smaller than half an ulp are lost).  The
- * context stays FP64 afterwards; no-op on FP64 contexts. */
+/* ASAGA_PREC_MIXED and ASAGA_PREC_F32 contexts: widen every instance's
+ * state to FP64 (x carried over exactly, alpha into a new FP64 array),
+ * recompute abar from alpha as asaga_reanchor does, and continue in FP64
+ * from there: the final polish, since FP32 x cannot hold the optimum more
+ * closely than its own rounding (and FP32 atomic additions smaller than
+ * half an ulp are lost).  The hot set keeps at most the FP64 layout's 5120
+ * columns.  The context stays FP64 afterwards; no-op on FP64 contexts. */
 int asaga_widen(asaga_ctx* ctx);
 
 /* Choose the number of wavefronts in flight and the step that reach
@@ -442,15 +443,28 @@ int asaga_widen(asaga_ctx* ctx);
  * ||grad f||^2 <= 2 lambda target f, which bounds (f - f*)/f by `target`
  * (f is lambda-strongly convex).  Smaller steps are probed while the
  * estimate improves (a step that fails does not end the search: above the
- * stable steps a short probe can pass by chance); a count whose probe alone
- * would take longer than the best estimate so far ends the search.  The six
- * best pairs (at most two steps per count) then run 3 * probe_epochs epochs
- * each, and the rate over the last third (closer to the asymptotic rate
- * than the short probe's) decides; a run already certified at a checkpoint
- * counts the epochs to the crossing, interpolated on log ||grad f||^2.
- * With FP32 x (ASAGA_PREC_MIXED, ASAGA_PREC_F32) a gradient norm at the floor FP32 rounding
- * leaves (8 * 2^-24 * L * ||x||) also counts as converged, so that stalling
- * there is not taken for instability.  The best pair is kept, the state is
+ * stable steps a short probe can pass by chance); the search ends once a
+ * count's probe alone would take four times the best estimate.  Short
+ * probes from x = 0 see mostly the early decrease: a step too large for its
+ * delay converges fastest there and then hovers at a noise floor, and with
+ * FP32 x a small step stalls at the floor FP32 additions leave.  So the
+ * finalists (per count its largest and next smaller stable steps and its
+ * best-estimated one, at most eight) race from x = 0, checked every
+ * probe_epochs / 3 epochs: a finalist finishes when the strong-convexity
+ * certificate holds (not the FP32 floor) or, at three checks in a row that
+ * agree on it, Aitken's limit of its last three objectives (after three
+ * falls of the objective and of the gradient norm, which a run hovering at a
+ * noise floor does not show) is within `target` of the last one (with FP32 x: a tenth of `target`, so
+ * that a run stalling at its FP32 floor just above it does not count), and
+ * drops out once its kernel time reaches the best finished one's, once it
+ * makes no new minimum for three checks, or after 40 * probe_epochs epochs.  The one finished in the least kernel
+ * time is kept (if none finishes, the one that got lowest); the
+ * report's est_epochs and est_seconds are then its measured epochs and
+ * kernel time.
+ * In the probes, with FP32 x (ASAGA_PREC_MIXED, ASAGA_PREC_F32), a gradient
+ * norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||) no longer
+ * has to fall, so that stalling there is not taken for instability; it
+ * certifies nothing (the objective then decides the estimate).  The best pair is kept, the state is
  * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair
  * was stable.
  * Batched contexts (opts.step and opts.waves must be 0) get the step law of

@@ -130,12 +130,16 @@ int fail(asaga_ctx* c, int code, const std::string& msg) {
     return code;
 }
 
+// On failure the runtime's last-error state is cleared too, so that a later
+// launch does not report this failure as its own.
 #define HIPCHK(ctx, call)                                                                          \
     do {                                                                                           \
         hipError_t e_ = (call);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
             return fail((ctx), e_ == hipErrorOutOfMemory ? ASAGA_E_OOM : ASAGA_E_HIP,              \
                         std::string(#call) + ": " + hipGetErrorString(e_));                        \
+        }                                                                                          \
     } while (0)
 
 template <typename T>
@@ -1296,6 +1300,9 @@ int asaga_widen(asaga_ctx* c) {
     c->mixed = false;
     c->layout = kLayF64;
     c->shape.layout = kLayF64;
+    // the FP64 layout's LDS holds at most kMaxHot hot columns
+    c->shape.hot = std::min(c->shape.hot, kMaxHot);
+    c->shape.tier = std::min(c->shape.tier, c->shape.hot);
     drop_graphs(c);
     // abar from the memory it averages, in FP64
     return asaga_reanchor(c);
@@ -1675,12 +1682,14 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     int tried = 0, rc = ASAGA_OK;
     // Run from x = 0 at step I.gamma with checkpoints cps[0..2]: false if
     // ||grad f|| did not decrease at every checkpoint; else the estimated
-    // epochs to ||g||^2 <= 2 lambda target f, with ||g|| taken to decay like
-    // exp(-r t) at the rate r of the last two checkpoints.
+    // epochs to the target by Aitken's extrapolation of the objective (else
+    // with ||g|| taken to decay like exp(-r t) at the rate r of the last two
+    // checkpoints, to ||g||^2 <= 2 lambda target f).
     auto probe = [&](const int* cps, double* est_e) -> bool {
         if ((rc = reset_state(c))) return false;
         double g2[3], f[3], x2 = 0.0;
         int done = 0;
+        bool at_floor = false;  // FP32 x: the gradient reached its rounding floor
         for (int k = 0; k < 3; ++k) {
             if ((rc = asaga_updates(c, (int64_t)(cps[k] - done) * I.m))) return false;
             done = cps[k];
@@ -1688,18 +1697,23 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             if (!(std::isfinite(g2[k]) && std::isfinite(f[k]))) return false;
             // already certified: later checkpoints would only see the noise
             // floor; the crossing is interpolated on log ||g||^2
-            const double goal_k = probe_goal(c, I, target, f[k], x2);
-            if (g2[k] <= goal_k) {
+            const double cert = 2.0 * I.lambda * target * f[k];
+            if (g2[k] <= cert) {
                 *est_e = (double)cps[k];
-                if (k > 0 && g2[k - 1] > goal_k && g2[k] > 0.0)
+                if (k > 0 && g2[k - 1] > cert && g2[k] > 0.0)
                     *est_e = (double)cps[k - 1] +
-                             (double)(cps[k] - cps[k - 1]) * std::log(g2[k - 1] / goal_k) / std::log(g2[k - 1] / g2[k]);
+                             (double)(cps[k] - cps[k - 1]) * std::log(g2[k - 1] / cert) / std::log(g2[k - 1] / g2[k]);
                 return true;
             }
+            // With FP32 x a gradient at the floor its rounding leaves need no
+            // longer fall; it certifies nothing (on strongly ill-conditioned
+            // data that floor is reached far from the optimum), so the
+            // objective then decides the estimate.
+            if (g2[k] <= probe_goal(c, I, target, f[k], x2)) at_floor = true;
             // one instance: the gradient norm must fall and the objective
             // must not rise at every checkpoint (slow instabilities pass a
             // looser test within a short probe)
-            if (k > 0 && !(g2[k] < g2[k - 1] && f[k] <= f[k - 1])) return false;
+            if (k > 0 && !((at_floor || g2[k] < g2[k - 1]) && f[k] <= f[k - 1])) return false;
         }
         int flag = 0;
         const hipError_t he = hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost);
@@ -1713,6 +1727,11 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         const double ea = aitken_epochs(f, cps, target);
         if (ea >= 0.0) {
             *est_e = ea;
+            return true;
+        }
+        if (at_floor) {
+            // no estimate from the objective: twice the probe, for the race
+            *est_e = 2.0 * (double)cps[2];
             return true;
         }
         const double r = probe_rate(g2, cps);
@@ -1737,9 +1756,11 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
             rc = fail(c, ASAGA_E_HIP, std::string("autotune timing: ") + hipGetErrorString(he));
             break;
         }
-        // every later shape is slower per epoch: none can beat the best once
-        // the probe alone takes longer than the best estimate
-        if ((double)probe_epochs * (double)ms * 1e-3 >= best.est_s) break;
+        // Every later shape is slower per epoch.  A short probe's estimate is
+        // too rough to rule the slower counts out (they tolerate larger
+        // steps), so the search ends only once the probe alone takes four
+        // times the best estimate so far.
+        if ((double)probe_epochs * (double)ms * 1e-3 >= 4.0 * best.est_s) break;
         // steps from the largest down, while the estimate improves: past the
         // best stable step, smaller steps only converge more slowly
         double shape_best = INFINITY;
@@ -1763,33 +1784,109 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         }
         if (rc) break;
     }
-    // The short probes see mostly the fast early decrease; the best
-    // candidates run three times longer, and the rate over their last third
-    // decides.
+    // The short probes from x = 0 see mostly the fast early decrease.  A
+    // step too large for its delay converges fastest there and then hovers
+    // at a noise floor; with FP32 x a small step stalls at the floor FP32
+    // additions leave.  Neither shows within a probe, so the finalists (per
+    // wavefront count its largest stable step, the next smaller one and its
+    // best-estimated one; at most eight, in order of their estimates) race
+    // from x = 0 with a check every probe_epochs / 3 epochs: a finalist
+    // finishes when the strong-convexity certificate holds or Aitken's
+    // extrapolation of its last three objectives puts it within the target
+    // of its limit (after three falling checks), and drops out once its
+    // kernel time reaches the best finished one's, once it stops reaching
+    // new minima for three checks (the noise floor), or after
+    // 40 * probe_epochs epochs.  The finalist finished in the least kernel
+    // time wins; if none finishes, the probes' ranking stands.
     if (!rc && stable_cands.size() > 1) {
-        std::sort(stable_cands.begin(), stable_cands.end(),
-                  [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });
-        // the two best steps of each wavefront count, six candidates in all
+        std::vector<Cand> by_est = stable_cands;
+        std::sort(by_est.begin(), by_est.end(), [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });
         std::vector<Cand> fin;
-        for (const Cand& k : stable_cands) {
-            int seen = 0;
-            for (const Cand& q : fin) seen += q.S.waves == k.S.waves ? 1 : 0;
-            if (seen < 2 && fin.size() < 6) fin.push_back(k);
+        auto add = [&](const Cand& k) {
+            for (const Cand& q : fin)
+                if (q.S.waves == k.S.waves && q.gamma == k.gamma) return;
+            if (fin.size() < 8) fin.push_back(k);
+        };
+        for (const Cand& k : by_est) {
+            // this count's largest and next smaller stable steps (candidates
+            // were recorded from the largest step down)
+            int taken = 0;
+            for (const Cand& q : stable_cands)
+                if (q.S.waves == k.S.waves && taken < 2) {
+                    add(q);
+                    ++taken;
+                }
+            add(k);
         }
-        stable_cands = fin;
-        const int cps3[3] = {probe_epochs, 2 * probe_epochs, 3 * probe_epochs};
+        std::sort(fin.begin(), fin.end(), [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });
+        // without a finisher: the finalist that got lowest while staying finite
+        Cand lowest;
+        double lowest_f = INFINITY;
+        // with FP32 x, a tenth of the target, so that a run stalling at its
+        // FP32 floor just above the target does not count as finished
+        const double tgt = c->mixed ? 0.1 * target : target;
         best = Cand{};
-        for (const Cand& k : stable_cands) {
+        const int chk = std::max(1, probe_epochs / 3);
+        const int max_e = 40 * probe_epochs;
+        for (const Cand& k : fin) {
             ++tried;
             c->shape = k.S;
             I.gamma = k.gamma;
-            double est_e = 0.0;
-            const bool ok = probe(cps3, &est_e);
+            if ((rc = reset_state(c))) break;
+            std::vector<double> fs, gs;
+            double fmin = INFINITY, prev_lim = NAN;
+            int since_min = 0, e = 0, agreed = 0;
+            bool finished = false;
+            while (e < max_e && !finished) {
+                if ((double)(e + chk) * k.ms * 1e-3 >= best.est_s) break;  // cannot beat the best
+                if ((rc = asaga_updates(c, (int64_t)chk * I.m))) break;
+                e += chk;
+                double g2 = 0.0, f = 0.0;
+                if ((rc = grad_norm2(c, 0, &g2, &f))) break;
+                if (!(std::isfinite(g2) && std::isfinite(f))) break;
+                // the strong-convexity certificate alone (the FP32 gradient
+                // floor of the probes holds long before the objective does)
+                if (g2 <= 2.0 * I.lambda * tgt * f) finished = true;
+                fs.push_back(f);
+                gs.push_back(g2);
+                if (f < fmin) {
+                    fmin = f;
+                    since_min = 0;
+                } else if (++since_min >= 3) {
+                    break;  // hovering: no new minimum for three checks
+                }
+                // Aitken's limit of the last three objectives (after three
+                // falls of the objective and of the gradient norm): finished
+                // when it is within tgt of the last objective at three checks
+                // in a row that agree on it.  A run converging to a noise
+                // floor instead of the optimum looks the same in the
+                // objective, but there the gradient norm stops falling.
+                const size_t n = fs.size();
+                double lim = NAN;
+                if (n >= 4 && fs[n - 1] < fs[n - 2] && fs[n - 2] < fs[n - 3] && fs[n - 3] < fs[n - 4] &&
+                    gs[n - 1] < gs[n - 2] && gs[n - 2] < gs[n - 3] && gs[n - 3] < gs[n - 4]) {
+                    const double d1 = fs[n - 2] - fs[n - 3], d2 = fs[n - 1] - fs[n - 2];
+                    if (d2 / d1 > 0.0 && d2 / d1 < 1.0) lim = fs[n - 1] - d2 * d2 / (d2 - d1);
+                }
+                const bool near = std::isfinite(lim) && fs[n - 1] - lim <= tgt * std::fabs(lim);
+                if (near && std::isfinite(prev_lim) && std::fabs(lim - prev_lim) <= tgt * std::fabs(lim))
+                    ++agreed;
+                else
+                    agreed = 0;
+                if (agreed >= 2) finished = true;
+                prev_lim = near ? lim : NAN;
+            }
             if (rc) break;
-            if (!ok) continue;
-            const double est_s = est_e * k.ms * 1e-3;
-            if (est_s < best.est_s) best = Cand{est_s, est_e, k.ms, k.gamma, k.S};
+            if (finished) {
+                const double est_s = (double)e * k.ms * 1e-3;
+                if (est_s < best.est_s) best = Cand{est_s, (double)e, k.ms, k.gamma, k.S};
+            }
+            if (fmin < lowest_f) {
+                lowest_f = fmin;
+                lowest = Cand{(double)e * k.ms * 1e-3, (double)e, k.ms, k.gamma, k.S};
+            }
         }
+        if (!rc && !std::isfinite(best.est_s) && std::isfinite(lowest_f)) best = lowest;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
