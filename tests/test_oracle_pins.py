@@ -339,7 +339,21 @@ def test_step_size_rule():
     p = datagen.config1()
     sv = oracle.SparseSaga(p)
     rows = np.add.reduceat(p.val ** 2, p.rowptr[:-1])
-    assert sv.L == pytest.approx(0.25 * rows.max() + p.lam, rel=1e-15)
+    # config 1's rows are L2-normalised, so the logistic smoothness constant
+    # is the value the paper's Section 4.1 table gives for the unit-norm RCV1
+    # rows, 0.25, plus the regulariser's lambda
+    assert rows.max() == pytest.approx(1.0, rel=1e-12)
+    assert sv.L == pytest.approx(0.25 + p.lam, rel=1e-12)
+    # 0.25 is the largest curvature of the logistic loss, phi''(0), here
+    # measured by central differences of the oracle's own phi'
+    h = 1e-5
+    curv = [(oracle.dphi(z + h, b, oracle.LOGISTIC) - oracle.dphi(z - h, b, oracle.LOGISTIC)) / (2 * h)
+            for z in np.linspace(-3, 3, 61) for b in (-1.0, 1.0)]
+    assert max(curv) == pytest.approx(0.25, rel=1e-8)
+    # squared loss: curvature 1, so L = max ||a_i||^2 + lambda
+    q = datagen.config3(n=3000)
+    assert oracle.SparseSaga(q).L == pytest.approx(np.add.reduceat(q.val ** 2, q.rowptr[:-1]).max() + q.lam,
+                                                   rel=1e-14)
     assert sv.gamma == pytest.approx(min(1 / (3 * sv.L), 1 / (p.lam * sv.D.max())), rel=1e-15)
     # the cap binds when lambda * max D is large
     q = datagen.config1(n=200, d=50, k=3)
