@@ -458,9 +458,9 @@ int asaga_widen(asaga_ctx* ctx);
  * that a run stalling at its FP32 floor just above it does not count), and
  * drops out once its kernel time reaches the best finished one's, once it
  * makes no new minimum for three checks, or after 40 * probe_epochs epochs.  The one finished in the least kernel
- * time is kept (if none finishes, the one that got lowest); the
- * report's est_epochs and est_seconds are then its measured epochs and
- * kernel time.
+ * time is kept, and the report's est_epochs and est_seconds are its
+ * measured epochs and kernel time to finish; if none finishes, the one
+ * that got lowest is kept, with the epochs it ran and their kernel time.
  * In the probes, with FP32 x (ASAGA_PREC_MIXED, ASAGA_PREC_F32), a gradient
  * norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||) no longer
  * has to fall, so that stalling there is not taken for instability; it
