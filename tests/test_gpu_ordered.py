@@ -225,3 +225,27 @@ def test_ordered_f32_state_follows_the_oracle_to_fp32_rounding(lanes):
         assert dx <= 1e-4 and da <= 1e-4
         runs[hot] = x
     assert rel_err(runs[512], runs[0]) <= 1e-4
+
+
+def test_ordered_batched_f32_state_follows_each_instance_oracle():
+    """The batched kernel in the FP32 layout, ordered: every instance's
+    iterate and memory follow its FP64 oracle to FP32 rounding, and its
+    running average holds to FP32 rounding."""
+    p = datagen.config2(n=6000, d=2500)
+    row_fold = datagen.folds5(p.n, seed=0)
+    inst_fold = np.array([1, -1, 4], dtype=np.int32)
+    inst_lam = np.array([3e-4, 1e-5, 1e-3])
+    with A.from_problem(p, mode=A.ASAGA_MODE_SERIAL, seed=3, precision=A.ASAGA_PREC_F32, lanes_per_sample=16,
+                        batch=(row_fold, inst_fold, inst_lam), **HOT) as g:
+        g.epochs(3)
+        for k, (f, lam) in enumerate(zip(inst_fold, inst_lam)):
+            rows = np.arange(p.n) if f < 0 else np.nonzero(row_fold != f)[0]
+            q = datagen.subproblem(p, rows, lam=float(lam))
+            sv = oracle.SparseSaga(q, seed=3 + k)
+            sv.epochs(3)
+            x, alpha, abar, t = g.get_state(k)
+            assert t == sv.state.t
+            dx, da = rel_err(x, sv.state.x), rel_err(alpha, sv.state.alpha)
+            inv = rel_err(abar, sv.memory_average(alpha))
+            say(f"ordered batched f32, instance {k}: x {dx:.1e}, alpha {da:.1e}, invariant {inv:.1e}")
+            assert dx <= 1e-4 and da <= 1e-4 and inv <= 1e-5

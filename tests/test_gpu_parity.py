@@ -458,6 +458,24 @@ def test_async_config4_full_reaches_1e9_autotuned(golden, precision):
         assert rel <= 1e-9
 
 
+@pytest.mark.slow
+def test_autotune_avoids_the_unstable_step_on_plain_lognormal_values(golden):
+    """Config 2 under its other value reading (lognormal values, no idf):
+    its stronger shared direction makes the benchmarked step (rule/8 at
+    4096 wavefronts) diverge; the autotuner's race must pick a shape and
+    step that reach 1e-9."""
+    p = datagen.config2(idf=False)
+    assert p.digest() == golden["config2_plain_lognormal"]["digest"]
+    fstar = golden["config2_plain_lognormal"]["f_lower"]
+    with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC) as g:
+        rep = g.autotune(target=1e-9, probe_epochs=9)
+        info = g.info()
+        ep, rel = run_to(g, fstar, max_epochs=300, every=2)
+        say(f"plain lognormal config2, autotuned: {info.waves} waves, {info.gamma * 3 * info.L:.3f} of the rule, "
+            f"race {rep.est_epochs:.0f} epochs: {ep} epochs, rel {rel:.2e}")
+        assert rel <= 1e-9
+
+
 def test_autotune_picks_a_stable_shape_and_converges():
     p = datagen.config2(n=30_000, d=6000)
     r = oracle.certified_fstar(p, tol=1e-12, check_every=10)
