@@ -1804,13 +1804,15 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     // wavefront count its largest stable step, the next smaller one and its
     // best-estimated one; at most eight, in order of their estimates) race
     // from x = 0 with a check every probe_epochs / 3 epochs: a finalist
-    // finishes when the strong-convexity certificate holds or Aitken's
-    // extrapolation of its last three objectives puts it within the target
-    // of its limit (after three falling checks), and drops out once its
+    // finishes when the strong-convexity certificate holds or when Aitken's
+    // limit of its last three objectives is within the target of the last
+    // one at three checks in a row that agree on it, after falls of the
+    // objective and of the gradient norm (below); it drops out once its
     // kernel time reaches the best finished one's, once it stops reaching
-    // new minima for three checks (the noise floor), or after
-    // 40 * probe_epochs epochs.  The finalist finished in the least kernel
-    // time wins; if none finishes, the probes' ranking stands.
+    // new minima for three checks (the noise floor), when a value turns
+    // non-finite, or after 40 * probe_epochs epochs.  The finalist finished
+    // in the least kernel time wins; if none finishes, the one that got
+    // lowest.
     if (!rc && stable_cands.size() > 1) {
         std::vector<Cand> by_est = stable_cands;
         std::sort(by_est.begin(), by_est.end(), [](const Cand& a, const Cand& b) { return a.est_s < b.est_s; });

@@ -64,6 +64,7 @@ def expect(code, **changes):
     kw = good()
     opts = {k: changes.pop(k) for k in list(changes) if k in ("mode", "precision", "lanes_per_sample", "racy",
                                                               "waves", "step", "loss", "hot_columns",
+                                                              "hot_tier_columns",
                                                               "flush_every", "threads_per_block",
                                                               "plain_launch", "method", "hot_reload_from")}
     kw.update(changes)
@@ -95,12 +96,16 @@ def test_bad_arguments_are_rejected():
     expect(E, lam=float("inf"))
     expect(E, mode=7)
     expect(E, precision=3)
+    expect(E, precision=-1)
     expect(E, lanes_per_sample=12)
     expect(E, racy=1)                                            # racy needs async mode
     expect(E, waves=-1)
     expect(E, step=float("nan"))
     expect(E, loss=5)
     expect(E, hot_columns=5121)
+    expect(E, hot_columns=5121, precision=A.ASAGA_PREC_MIXED)
+    expect(E, hot_columns=10241, precision=A.ASAGA_PREC_F32)      # the FP32 layout holds up to 10240
+    expect(E, hot_tier_columns=10241, precision=A.ASAGA_PREC_F32)
     expect(E, hot_columns=-2)
     expect(E, flush_every=-1)
     expect(E, threads_per_block=100)
