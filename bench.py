@@ -947,27 +947,36 @@ def main():
         log(f"memory-side requests: {total:.3e}/s = {total / ceil_mixed:.2f} of the ceiling")
 
     # ---- time to 1e-9 relative suboptimality from a cold start ----------------
-    def time_to_target(step, shape):
-        g = make_solver(step, shape)
-        ti = g.info()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        kernel_s = 0.0
-        rel = float("inf")
-        epochs = 0
-        while epochs < 100:
-            e0.record(stream)
-            g.epochs(1)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            kernel_s += e0.elapsed_time(e1) / 1e3
-            epochs += 1
-            rel = (g.objective() - fstar) / fstar
-            if rel <= 1e-9:
-                break
-        g.close()
-        return {"target": 1e-9, "reached": rel <= 1e-9, "epochs": epochs, "seconds": kernel_s,
-                "final_rel_subopt": rel, "waves": ti.waves, "threads_per_block": ti.threads_per_block,
-                "hot_columns": ti.hot_columns, "gamma": ti.gamma, "gamma_over_serial_rule": ti.gamma * 3.0 * ti.L}
+    def time_to_target(step, shape, runs=5):
+        """Kernel seconds to 1e-9 from x = 0, the median of `runs` runs
+        (each checked after every epoch, the checks not timed)."""
+        res = []
+        for _ in range(runs):
+            g = make_solver(step, shape)
+            ti = g.info()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            kernel_s = 0.0
+            rel = float("inf")
+            epochs = 0
+            while epochs < 100:
+                e0.record(stream)
+                g.epochs(1)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                kernel_s += e0.elapsed_time(e1) / 1e3
+                epochs += 1
+                rel = (g.objective() - fstar) / fstar
+                if rel <= 1e-9:
+                    break
+            g.close()
+            res.append((kernel_s, epochs, rel))
+        secs = sorted(r[0] for r in res)
+        mid = sorted(res)[len(res) // 2]
+        return {"target": 1e-9, "reached": all(r[2] <= 1e-9 for r in res), "epochs": mid[1], "seconds": mid[0],
+                "runs": runs, "seconds_each": [r[0] for r in res], "epochs_each": [r[1] for r in res],
+                "seconds_min": secs[0], "seconds_max": secs[-1], "final_rel_subopt": mid[2], "waves": ti.waves,
+                "threads_per_block": ti.threads_per_block, "hot_columns": ti.hot_columns, "gamma": ti.gamma,
+                "gamma_over_serial_rule": ti.gamma * 3.0 * ti.L}
 
     tta = tta_tuned = tta_svrg = None
     if not args.skip_tta:
@@ -1020,6 +1029,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": total_ms / args.steps,
+        "ms_per_step_median": sorted(launch_ms)[len(launch_ms) // 2],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
