@@ -459,6 +459,36 @@ def test_async_config4_full_reaches_1e9_autotuned(golden, precision):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("name", ["config1", "config3", "config4"])
+def test_batched_f32_state_reaches_1e9_on_the_other_workloads(golden, name):
+    """The batched kernel (persistent grid, captured graph, the batched
+    autotuner's step law) in FP32 state on the tiny, Covtype-shaped and
+    URL-shaped workloads, each as a batch of one instance: to 1e-9 of the
+    stored optimum, widened to FP64 for the polish once FP32 stalls."""
+    p = datagen.by_name(name)
+    assert p.digest() == golden[name]["digest"]
+    fstar = golden[name]["f_lower"]
+    bf16 = p.val_bf16 is not None
+    with A.from_problem(p, bf16=bf16, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_F32,
+                        batch=(None, np.array([-1], np.int32), np.array([p.lam]))) as g:
+        rep = g.autotune(target=1e-9, probe_epochs=6)
+        ep, rel, hist = 0, np.inf, []
+        while ep < 600 and rel > 1e-9 and not (len(hist) > 4 and min(hist[-4:]) > 0.8 * min(hist[:-4])):
+            g.epochs(5)
+            ep += 5
+            rel = (g.objective() - fstar) / fstar
+            hist.append(rel)
+        ep64 = 0
+        if rel > 1e-9:
+            g.widen()
+            ep64, rel = run_to(g, fstar, max_epochs=600, every=5)
+        ins = g.instance(0)
+        say(f"batched f32, {name}: law c = {rep.step_groups:.0f}, cap {rep.step_cap}, {rep.waves} waves, "
+            f"gamma {ins.gamma:.4g}: {ep} FP32 + {ep64} FP64 epochs, rel {rel:.2e}")
+        assert rel <= 1e-9
+
+
+@pytest.mark.slow
 def test_autotune_avoids_the_unstable_step_on_plain_lognormal_values(golden):
     """Config 2 under its other value reading (lognormal values, no idf):
     its stronger shared direction makes the benchmarked step (rule/8 at
