@@ -19,8 +19,9 @@
 //     is reduced inside the group with cross-lane shuffles;
 //   * the write phase works in lane pairs, one row entry per pair: the even
 //     lane carries x_c, the odd lane abar_c.  x and abar are interleaved per
-//     column (16 bytes), so the pair's load and the pair's atomic add are
-//     each one memory request;
+//     column (16 bytes in FP64, 8 in the FP32 layout), so the pair's load and
+//     the pair's atomic add are each one memory request (in the mixed layout,
+//     FP32 x beside FP64 abar, the add takes two);
 //   * rows of up to 2G entries keep their column indices, values and state
 //     in registers between the read and the write phase; longer rows are
 //     processed in chunks and read again;
@@ -175,10 +176,12 @@ __device__ __forceinline__ double group_sum(double v) {
 // the Sparse SAGA update of one sample, applied by a group of G lanes
 // ---------------------------------------------------------------------------
 
-// The (x_c, abar_c) pair of column c: one 16-byte load with the sc1 cache
-// policy (served from the device-coherent level, like an agent-scope
-// atomic load), through a buffer descriptor whose range check returns zeros
-// for an offset past the state (the CDNA descriptor word 3 is 0x00020000).
+// The (x_c, abar_c) pair of column c: one 16-byte load (FP32 layout: 8
+// bytes) with the sc1 cache policy (served from the device-coherent level,
+// like an agent-scope atomic load; lines that atomics modify are served from
+// there whatever the policy), through a buffer descriptor whose range check
+// returns zeros for an offset past the state (the CDNA descriptor word 3 is
+// 0x00020000).
 struct Pair {
     double x, a;
 };
