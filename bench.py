@@ -558,7 +558,8 @@ def config3_leg(dev, stream):
     out["fp32_then_fp64"] = {"fp32_epochs": ep32, "fp32_seconds": s32, "rel_subopt_fp32": rel32,
                              "fp64_epochs": ep64, "fp64_seconds": s64, "final_rel_subopt": rel64,
                              "reached": rel64 <= 1e-9, "seconds_to_1e-9": s32 + s64,
-                             "fp32_updates_per_s": ep32 * p.n / s32 if s32 > 0 else None}
+                             "fp32_updates_per_s": ep32 * p.n / s32 if s32 > 0 else None,
+                             "waves": rep.waves, "gamma": rep.gamma, "fp64_polish_gamma": rep.widen_gamma}
     g.close()
     log(f"config3 FP32 then FP64: {out['fp32_then_fp64']}")
     return out
@@ -623,6 +624,7 @@ def config4_leg(dev, stream, p=None):
            "fp32_hbm_gbps_algorithmic": bpu * ep32 * p.n / secs32 / 1e9 if secs32 > 0 else None,
            "bytes_per_update_fp32": bpu, "waves": info.waves, "threads_per_block": info.threads_per_block,
            "hot_columns": info.hot_columns, "gamma": info.gamma, "gamma_over_serial_rule": info.gamma * 3.0 * info.L,
+           "fp64_polish_gamma": rep.widen_gamma if ep64 else None,
            "autotune_wall_s": tune_s, "autotune_race_epochs": rep.est_epochs}
     log(f"config4: {out}")
     return out

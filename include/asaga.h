@@ -278,6 +278,10 @@ typedef struct asaga_tune_report {
                                  instance k (at most step_groups / step_cap);
                                  one solve: 0                                      */
     double step_cap;
+    double widen_gamma;       /* the step asaga_widen switches to: gamma, or with
+                                 FP32 x, when gamma is the largest stable step
+                                 probed at its wavefront count, the next smaller
+                                 one (gamma * 2^(-1/3)); batches: gamma         */
 } asaga_tune_report;
 
 /* Create a context for the problem of Section 1 (Eq. finiteSum with the
@@ -421,7 +425,13 @@ int asaga_reanchor(asaga_ctx* ctx);
  * from there: the final polish, since FP32 x cannot hold the optimum more
  * closely than its own rounding (and FP32 atomic additions smaller than
  * half an ulp are lost).  The hot set keeps at most the FP64 layout's 5120
- * columns.  The context stays FP64 afterwards; no-op on FP64 contexts. */
+ * columns.  The launch shape and the step are kept, except after
+ * asaga_autotune chose the largest stable step it probed at its wavefront
+ * count: then the polish takes the next smaller step of the tuner's ladder
+ * (report.widen_gamma).  The FP64 kernel serves its atomics faster than the
+ * FP32 state's, so at the same launch more updates are in flight, and the
+ * largest stable step shrinks with them (Theorem 2).  The context stays FP64
+ * afterwards; no-op on FP64 contexts. */
 int asaga_widen(asaga_ctx* ctx);
 
 /* Choose the number of wavefronts in flight and the step that reach
@@ -464,7 +474,9 @@ int asaga_widen(asaga_ctx* ctx);
  * In the probes, with FP32 x (ASAGA_PREC_MIXED, ASAGA_PREC_F32), a gradient
  * norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||) no longer
  * has to fall, so that stalling there is not taken for instability; it
- * certifies nothing (the objective then decides the estimate).  The best pair is kept, the state is
+ * certifies nothing (the objective then decides the estimate); if the pair
+ * kept has the largest stable step probed at its count, asaga_widen lowers
+ * it one rung (report.widen_gamma).  The best pair is kept, the state is
  * reset to x = alpha = abar = 0, t = 0.  Returns ASAGA_E_DIVERGED if no pair
  * was stable.
  * Batched contexts (opts.step and opts.waves must be 0) get the step law of

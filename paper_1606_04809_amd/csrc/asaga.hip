@@ -79,6 +79,7 @@ struct asaga_ctx {
     hipStream_t st = nullptr;
     bool mixed = false;          // FP32 x and alpha (mixed and FP32 layouts)
     int layout = kLayF64;        // kLay*: the state layout of ASAGA_PREC_*
+    double widen_gamma = 0.0;    // step asaga_widen switches to (0: keep the step)
     bool svrg = false;           // ASAGA_METHOD_SVRG
     UpdateShape shape{};
     std::vector<Inst> inst;
@@ -1313,6 +1314,8 @@ int asaga_widen(asaga_ctx* c) {
     c->mixed = false;
     c->layout = kLayF64;
     c->shape.layout = kLayF64;
+    if (c->widen_gamma > 0.0 && !c->d_insts) c->inst[0].gamma = c->widen_gamma;
+    c->widen_gamma = 0.0;
     // the FP64 layout's LDS holds at most kMaxHot hot columns
     c->shape.hot = std::min(c->shape.hot, kMaxHot);
     c->shape.tier = std::min(c->shape.tier, c->shape.hot);
@@ -1652,6 +1655,7 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         rep->est_seconds = best.est_s;
         rep->step_groups = c->step_groups;
         rep->step_cap = c->step_cap;
+        rep->widen_gamma = c->inst[0].gamma;
     }
     return ASAGA_OK;
 }
@@ -1663,6 +1667,7 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     if (c->shape.serial) return fail(c, ASAGA_E_STATE, "autotuning needs an async context");
     if (!(target > 0.0 && target < 1.0)) return fail(c, ASAGA_E_ARG, "target must be in (0, 1)");
     if (probe_epochs < 3 || probe_epochs > 1000) return fail(c, ASAGA_E_ARG, "probe_epochs must be in [3, 1000]");
+    c->widen_gamma = 0.0;
     if (c->d_insts) return autotune_batched(c, target, probe_epochs, rep);
     Inst& I = c->inst[0];
     const UpdateShape base = c->shape;
@@ -1917,6 +1922,20 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     }
     c->shape = best.S;
     I.gamma = best.gamma;
+    // With FP32 state the run ends with an FP64 polish after asaga_widen.
+    // The FP64 kernel serves its atomics faster, so at the same launch more
+    // updates are in flight and, by Theorem 2, its largest stable step is
+    // smaller: the Covtype-shaped instance at 1024 wavefronts overlaps 2587
+    // updates in FP64 against 1615 with FP32 x and FP64 abar, and diverges in
+    // FP64 at the largest step stable there.  When the choice is the largest
+    // stable step probed at its count, the polish takes the next smaller one.
+    c->widen_gamma = 0.0;
+    if (c->mixed)
+        for (const Cand& q : stable_cands)
+            if (q.S.waves == best.S.waves) {  // recorded from the largest step down
+                if (q.gamma == best.gamma) c->widen_gamma = best.gamma * std::exp2(-1.0 / 3.0);
+                break;
+            }
     if ((rc = reset_state(c))) return rc;
     if (rep) {
         rep->candidates = tried;
@@ -1929,6 +1948,7 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
         rep->est_seconds = best.est_s;
         rep->step_groups = 0.0;
         rep->step_cap = 0.0;
+        rep->widen_gamma = c->widen_gamma > 0.0 ? c->widen_gamma : best.gamma;
     }
     return ASAGA_OK;
 }

@@ -406,14 +406,21 @@ def test_async_config3_full_fp64_reaches_1e9(golden):
 def test_mixed_precision_then_fp64_polish_config3_full(golden):
     """FP32 x cannot hold the Covtype-shaped optimum to 1e-9 (its rounding
     alone moves f by more); asaga_widen switches to FP64 state, re-anchors
-    abar from alpha, and the FP64 epochs that follow reach 1e-9."""
+    abar from alpha, and the FP64 epochs that follow reach 1e-9.  The mixed
+    kernel's slow FP32 atomics on the ten shared columns keep fewer updates
+    in flight than the FP64 kernel at the same launch, so the largest step
+    stable with FP32 x can diverge in FP64 (Theorem 2): when the tuner chose
+    that step, the polish takes the next smaller one."""
     p = datagen.config3()
     assert p.digest() == golden["config3"]["digest"]
     fstar = golden["config3"]["f_star"]
     with A.from_problem(p, mode=A.ASAGA_MODE_ASYNC, precision=A.ASAGA_PREC_MIXED) as g:
         rep = g.autotune(target=1e-9, probe_epochs=9)
+        say(f"config3 mixed: tuned waves {rep.waves} gamma {rep.gamma:.4g}, polish step {rep.widen_gamma:.4g}")
+        assert rep.widen_gamma in (rep.gamma, rep.gamma * 2.0 ** (-1.0 / 3.0))
         ep32, rel32 = run_to(g, fstar, max_epochs=100, every=10)
         g.widen()
+        assert g.info().gamma == rep.widen_gamma and g.info().waves == rep.waves
         x, alpha, abar, t = g.get_state()
         assert rel_err(abar, oracle.SparseSaga(p).memory_average(alpha)) < 1e-12
         f_widened = g.objective()
@@ -451,6 +458,7 @@ def test_async_config4_full_reaches_1e9_autotuned(golden, precision):
         if rel > 1e-9:
             # FP32 x stalled above the target: the FP64 polish finishes
             g.widen()
+            assert g.info().gamma == rep.widen_gamma
             ep64, rel = run_to(g, fstar, max_epochs=400, every=5)
         say(f"config4 {precision}, autotuned: {info.waves} waves, gamma {info.gamma:.4g} "
             f"({info.gamma * 3 * info.L:.3f} of the serial rule), {rep.ms_per_epoch:.1f} ms/epoch, "
