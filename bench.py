@@ -158,16 +158,79 @@ def tau_sweep(p, dev_arrays, fstar, stream):
     return {"step_over_serial_rule": 1.0 / 16, "points": out}
 
 
+def solve_with_stop_test(g, check, stream, target=1e-9, max_launches=600, eager=2.0, max_gap=8, label=""):
+    """Run every instance of a batch to `target`, the in-graph stop test
+    choosing which instances the host checks exactly.  Each step is one
+    epoch call: the batched launch, then on the device the O(d) proxy r_k =
+    ||abar_k + lambda_k x_k||^2 of every running instance, which switches
+    off those at or below their threshold.  The host then checks exactly
+    (check(k): relative suboptimality from FP64 objectives) only the
+    instances the test switched off, those never checked and those
+    unchecked for `max_gap` epochs.  A check below `target` ends the
+    instance; otherwise it (re)calibrates the threshold to the proxy at
+    which rel/proxy as measured there would put the instance at eager *
+    target, and an instance the test stopped early runs on.  Returns the
+    kernel seconds between HIP events, the counts of launches, checks and
+    early stops, and each instance's last checked value and samples."""
+    import numpy as np
+    import torch
+
+    ni = g.n_inst
+    active = np.ones(ni, dtype=np.uint8)
+    rel = np.full(ni, np.inf)
+    thr = np.zeros(ni)                       # 0: not calibrated, never stops
+    last = np.full(ni, -(10 ** 9))
+    applied = np.zeros(ni, dtype=np.int64)
+    g.set_active(active)
+    g.set_stop(thr)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kernel_s, launches, checks, early, pairs = 0.0, 0, 0, 0, 0
+    while active.any() and launches < max_launches:
+        pairs += int(active.sum())
+        e0.record(stream)
+        g.epochs(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kernel_s += e0.elapsed_time(e1) / 1e3
+        launches += 1
+        proxy, _ = g.stop_report()
+        for k in np.nonzero(active)[0]:
+            stopped = thr[k] > 0.0 and proxy[k] <= thr[k]   # the device's rule, same doubles
+            if not (stopped or thr[k] == 0.0 or launches - last[k] >= max_gap):
+                continue
+            checks += 1
+            last[k] = launches
+            rel[k] = check(int(k))
+            if rel[k] <= target:
+                active[k] = 0
+                applied[k] = g.instance(int(k)).t
+                continue
+            early += int(stopped)
+            thr[k] = eager * target * proxy[k] / rel[k] if rel[k] > 0.0 and proxy[k] > 0.0 else 0.0
+        g.set_stop(thr)
+        g.set_active(active)
+        if label and (launches % 8 == 0 or not active.any()):
+            log(f"{label}: {launches} launches, {int(active.sum())} instances still active, "
+                f"{checks} exact checks, kernel {kernel_s:.3f} s")
+    g.set_stop(None)
+    for k in np.nonzero(active)[0]:
+        applied[k] = g.instance(int(k)).t
+    return {"kernel_s": kernel_s, "launches": launches, "checks": checks, "early_stops": early, "rel": rel,
+            "applied": applied, "instance_launches": pairs}
+
+
 def batched_leg(args, dev, stream):
     """The lambda path x folds workload (160 instances over the bfloat16
     config-2 matrix): all instances in one persistent kernel per epoch,
     replayed from a captured hipGraph, autotuned wavefronts per instance,
     hot-set size and step; each instance is switched off once it is within
-    1e-9 of its certified optimum.  Three state precisions: FP32 x, alpha
+    1e-9 of its certified optimum, the in-graph stop test choosing which
+    instances the host checks exactly after each launch.  Three state precisions: FP32 x, alpha
     and abar in 8-byte slots (the headline), mixed (FP32 x and alpha, FP64
     abar) and FP64; then the same instances one by one with the plain FP64
-    async kernel.  Kernel times are between HIP events; the objective checks
-    between them (after every launch) are not counted there, and the
+    async kernel.  Kernel times (the stop test's O(d) kernels included) are
+    between HIP events; the exact objective checks between launches are not
+    counted there, and the
     end-to-end wall time of each batched solve, checks and re-planning
     included, is reported beside it."""
     import numpy as np
@@ -214,33 +277,14 @@ def batched_leg(args, dev, stream):
                 "gamma_inst0": rep.gamma, "step_groups": rep.step_groups, "step_cap": rep.step_cap,
                 "ms_per_epoch": rep.ms_per_epoch, "est_epochs": rep.est_epochs, "tuning_wall_s": time.time() - t}
         log(f"batched {label} autotune: {tune}")
-        active = np.ones(ni, dtype=np.uint8)
-        rel = np.full(ni, np.inf)
         # samples each instance applied (with automatic waves an instance
         # holding more workgroups than others applies more per launch)
-        applied = np.zeros(ni, dtype=np.int64)
-        kernel_s, launches, check = 0.0, 0, 1
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        while active.any() and launches < 600:
-            e0.record(stream)
-            g.epochs(check)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            kernel_s += e0.elapsed_time(e1) / 1e3
-            launches += check
-            for k in np.nonzero(active)[0]:
-                rel[k] = (g.objective(int(k)) - fstar[k]) / fstar[k]
-                if rel[k] <= 1e-9:
-                    active[k] = 0
-                    applied[k] = g.instance(int(k)).t
-            g.set_active(active)
-            if launches % 8 == 0 or not active.any():
-                log(f"batched {label}: {launches} launches, {int(active.sum())} instances still active, "
-                    f"kernel {kernel_s:.3f} s")
+        res = solve_with_stop_test(g, lambda k: (g.objective(k) - fstar[k]) / fstar[k], stream,
+                                   label=f"batched {label}")
         wall_s = time.perf_counter() - w0
-        for k in np.nonzero(active)[0]:
-            applied[k] = g.instance(int(k)).t
+        kernel_s, launches, rel, applied = res["kernel_s"], res["launches"], res["rel"], res["applied"]
         hot = g.info().hot_columns
         g.close()
         epochs = applied / m
@@ -249,6 +293,8 @@ def batched_leg(args, dev, stream):
         bpu = 4 + 16 + 8 + 6 * mean_k + 2 * s_alpha
         gbps = bpu * updates / kernel_s / 1e9
         return {"instances": ni, "reached": int(np.sum(rel <= 1e-9)), "launches": launches,
+                "exact_checks": res["checks"], "early_stops": res["early_stops"],
+                "exact_checks_if_every_launch": res["instance_launches"],
                 "epochs_max": float(epochs.max()), "epochs_median": float(np.median(epochs)),
                 "seconds_to_1e-9_all": kernel_s, "wall_seconds_to_1e-9_all": wall_s, "updates": updates,
                 "updates_per_s": updates / kernel_s, "worst_rel_subopt": float(np.max(rel)),

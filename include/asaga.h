@@ -325,7 +325,12 @@ int asaga_init_batched(asaga_ctx** out, const asaga_problem* prob, const asaga_o
  * (up to 64; larger counts run in pieces) into a hipGraph on a private
  * stream and replayed on the context's stream (unless opts.plain_launch).  It waits for the previous call's work before
  * rewriting the per-instance descriptors and the workgroup map the kernels
- * read. */
+ * read.  With the stop test armed (asaga_set_stop) each epoch's launch is
+ * followed by the test, and the call waits for its launches before it
+ * returns: the instances the test switched off are then off
+ * (asaga_instance_get), and their sample counters count the epochs they
+ * ran.  Pieces of a call past 64 epochs share the running instances'
+ * workgroups anew. */
 int asaga_epochs(asaga_ctx* ctx, int64_t n_epochs);
 
 /* Batched contexts: switch instances on (1) or off (0) for later
@@ -334,6 +339,37 @@ int asaga_epochs(asaga_ctx* ctx, int64_t n_epochs);
  * The usual use: switch off each instance once its certificate or
  * validation check has met the tolerance. */
 int asaga_set_active(asaga_ctx* ctx, const uint8_t* active);
+
+/* Batched contexts: arm the stop test of asaga_epochs with one threshold
+ * per instance (thresholds is double[n_inst], each >= 0; +infinity stops an
+ * instance after its first epoch), or disarm it (thresholds = NULL).  After
+ * every epoch of a call, a kernel on the same stream computes for each
+ * instance still running
+ *     r_k = || abar_k + lambda_k x_k ||^2,
+ * in FP64 over all d columns: abar is the average of the memory (Section 2,
+ * the running average of Eq. SparseSAGA, a_j scaled by each row's stored
+ * derivative alpha_j), so abar + lambda x is the objective's full gradient
+ * (the Section 4.1 objective) with every alpha_j taken from when row j was
+ * last sampled instead of at the current x.  It costs O(d) per instance,
+ * not a pass over the rows.  An instance with r_k <= thresholds[k] applies
+ * no more samples in that call and is switched off when it returns.  The
+ * proxy is not the gradient: a threshold 2 lambda_k eps f_k (f_k at or
+ * below the optimum's value) would certify (f - f*)/f* <= eps through strong
+ * convexity only for the exact gradient (asaga_full_grad), so a caller
+ * confirms a switched-off instance with the exact FP64 objective or
+ * gradient and switches it on again if the check fails.  The thresholds
+ * are copied; the call waits for the context's stream.  The autotuner runs
+ * without the test.  Errors: ASAGA_E_STATE (not batched), ASAGA_E_ARG (a
+ * threshold below 0 or NaN), ASAGA_E_OOM (first call: three arrays of
+ * n_inst entries). */
+int asaga_set_stop(asaga_ctx* ctx, const double* thresholds);
+
+/* Batched contexts: what the stop test saw in the last asaga_epochs call
+ * with it armed.  proxy_out (double[n_inst], or NULL): r_k after the last
+ * epoch instance k ran in that call (NaN if it ran none); epochs_out
+ * (int64_t[n_inst], or NULL): the epochs (launches) it ran, fewer than the
+ * call's where the test switched it off.  Before any such call: NaN and 0. */
+int asaga_stop_report(asaga_ctx* ctx, double* proxy_out, int64_t* epochs_out);
 
 /* Apply `count` samples (single-instance contexts only).  With
  * ASAGA_METHOD_SVRG, `count` iterations, the full-gradient ones included

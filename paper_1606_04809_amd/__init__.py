@@ -122,6 +122,8 @@ _SIGS = {
                                           ctypes.POINTER(asaga_opts), ctypes.POINTER(asaga_batch)]),
     "asaga_epochs": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "asaga_set_active": (ctypes.c_int, [_CTX, _P]),
+    "asaga_set_stop": (ctypes.c_int, [_CTX, _P]),
+    "asaga_stop_report": (ctypes.c_int, [_CTX, _P, _P]),
     "asaga_updates": (ctypes.c_int, [_CTX, ctypes.c_int64]),
     "asaga_objective": (ctypes.c_int, [_CTX, ctypes.c_int32, _P, ctypes.POINTER(ctypes.c_double)]),
     "asaga_objective_noalloc": (ctypes.c_int, [ctypes.POINTER(asaga_problem), _P, _P, _P]),
@@ -195,6 +197,20 @@ def asaga_epochs(ctx, n_epochs: int):
 def asaga_set_active(ctx, active):
     a = np.ascontiguousarray(active, dtype=np.uint8)
     return _check(_lib.asaga_set_active(ctx, a.ctypes.data), ctx)
+
+
+def asaga_set_stop(ctx, thresholds):
+    if thresholds is None:
+        return _check(_lib.asaga_set_stop(ctx, None), ctx)
+    t = np.ascontiguousarray(thresholds, dtype=np.float64)
+    return _check(_lib.asaga_set_stop(ctx, t.ctypes.data), ctx)
+
+
+def asaga_stop_report(ctx, n_inst: int):
+    proxy = np.empty(n_inst, dtype=np.float64)
+    epochs = np.empty(n_inst, dtype=np.int64)
+    _check(_lib.asaga_stop_report(ctx, proxy.ctypes.data, epochs.ctypes.data), ctx)
+    return proxy, epochs
 
 
 def asaga_updates(ctx, count: int):
@@ -398,6 +414,18 @@ class Solver:
         if len(active) != self.n_inst:
             raise ValueError(f"expected {self.n_inst} flags")
         asaga_set_active(self.ctx, active)
+
+    def set_stop(self, thresholds):
+        """Arm the in-graph stop test with one threshold per instance, or
+        disarm it (None)."""
+        if thresholds is not None and len(thresholds) != self.n_inst:
+            raise ValueError(f"expected {self.n_inst} thresholds")
+        asaga_set_stop(self.ctx, thresholds)
+
+    def stop_report(self):
+        """(proxy, epochs): the stop test's last proxy and the epochs each
+        instance ran in the last call with it armed."""
+        return asaga_stop_report(self.ctx, self.n_inst)
 
     def objective(self, inst: int = 0, x=None) -> float:
         return asaga_objective(self.ctx, inst, self.d, x)

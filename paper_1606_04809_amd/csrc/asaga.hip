@@ -94,13 +94,24 @@ struct asaga_ctx {
     // G_k the lane groups serving instance k (0: not calibrated, use
     // kStepGroups, the single-instance default)
     double step_groups = 0.0, step_cap = 1.0;
-    // batched: captured epochs, keyed by epochs per replay, tier interval, grid
+    // batched stop test (asaga_set_stop): per-instance thresholds, the proxy
+    // after the last epoch each instance ran, the epochs each ran in a call
+    // (device), and the last call's copies (host)
+    bool stop_on = false;
+    double* d_stop_thr = nullptr;
+    double* d_proxy = nullptr;
+    int32_t* d_ran = nullptr;
+    std::vector<double> proxy_h;
+    std::vector<int64_t> ran_h;
+    // batched: captured epochs, keyed by epochs per replay, tier interval,
+    // grid and whether the stop test follows each epoch
     hipStream_t cap = nullptr;
     struct Captured {
         int64_t epochs;
         int tier_every, hot, tier;
         int n_blocks;
         const void* map;
+        bool stop;
         hipGraph_t graph;
         hipGraphExec_t exec;
     };
@@ -956,19 +967,23 @@ int plan_batched(asaga_ctx* c, UpdateShape* Sout) {
 
 // The hipGraph that applies `epochs` epochs of the planned launch: one
 // batched launch per epoch, epoch index e in 0..epochs-1 baked into each
-// node.  The descriptors and block map it reads are rewritten before each
-// replay.
+// node, each followed by the stop test when it is armed.  The descriptors
+// and block map it reads are rewritten before each replay.
 int epochs_graph(asaga_ctx* c, int64_t epochs, const UpdateShape& S, int n_blocks, hipGraphExec_t* out) {
     for (const auto& g : c->graphs)
         if (g.epochs == epochs && g.tier_every == S.tier_every && g.hot == S.hot && g.tier == S.tier &&
-            g.n_blocks == n_blocks && g.map == c->d_map) {
+            g.n_blocks == n_blocks && g.map == c->d_map && g.stop == c->stop_on) {
             *out = g.exec;
             return ASAGA_OK;
         }
     HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
     hipError_t le = hipSuccess;
-    for (int64_t e = 0; e < epochs && le == hipSuccess; ++e)
+    for (int64_t e = 0; e < epochs && le == hipSuccess; ++e) {
         le = launch_updates_batched(mat(c), c->d_insts, c->d_map, n_blocks, (uint64_t)e, S, c->flag, c->cap);
+        if (le == hipSuccess && c->stop_on)
+            le = launch_batch_proxy(c->d_insts, (int)c->inst.size(), c->d, S.layout, c->d_stop_thr, c->d_proxy,
+                                    c->d_ran, (int32_t)e, c->cap);
+    }
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -983,7 +998,7 @@ int epochs_graph(asaga_ctx* c, int64_t epochs, const UpdateShape& S, int n_block
         (void)hipGraphDestroy(graph);
         return fail(c, ASAGA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     }
-    c->graphs.push_back({epochs, S.tier_every, S.hot, S.tier, n_blocks, c->d_map, graph, exec});
+    c->graphs.push_back({epochs, S.tier_every, S.hot, S.tier, n_blocks, c->d_map, c->stop_on, graph, exec});
     *out = exec;
     return ASAGA_OK;
 }
@@ -1001,16 +1016,43 @@ int batched_piece(asaga_ctx* c, int64_t epochs) {
                              hipMemcpyHostToDevice, c->st));
     HIPCHK(c, hipMemcpyAsync(c->d_map, c->plan_map.data(), c->plan_map.size() * sizeof(BlockMap),
                              hipMemcpyHostToDevice, c->st));
+    const int ni = (int)c->inst.size();
+    if (c->stop_on) {
+        HIPCHK(c, launch_fill_i32(c->d_ran, 0, ni, c->st));
+        HIPCHK(c, launch_fill_f64(c->d_proxy, std::nan(""), ni, 1, c->st));
+    }
     if (c->o.plain_launch) {
-        for (int64_t e = 0; e < epochs; ++e)
+        for (int64_t e = 0; e < epochs; ++e) {
             HIPCHK(c, launch_updates_batched(mat(c), c->d_insts, c->d_map, n_blocks, (uint64_t)e, S, c->flag, c->st));
+            if (c->stop_on)
+                HIPCHK(c, launch_batch_proxy(c->d_insts, ni, c->d, S.layout, c->d_stop_thr, c->d_proxy, c->d_ran,
+                                             (int32_t)e, c->st));
+        }
     } else {
         hipGraphExec_t exec = nullptr;
         if ((rc = epochs_graph(c, epochs, S, n_blocks, &exec))) return rc;
         HIPCHK(c, hipGraphLaunch(exec, c->st));
     }
-    for (size_t k = 0; k < c->inst.size(); ++k)
-        if (c->inst[k].active) c->inst[k].t += epochs * (int64_t)c->plan_h[k].count;
+    if (!c->stop_on) {
+        for (int k = 0; k < ni; ++k)
+            if (c->inst[k].active) c->inst[k].t += epochs * (int64_t)c->plan_h[k].count;
+        return ASAGA_OK;
+    }
+    // the stop test: wait for the launches, then take the instances it
+    // switched off out of the plan and count the epochs each one ran
+    std::vector<int32_t> ran(ni);
+    std::vector<double> proxy(ni);
+    HIPCHK(c, hipMemcpyAsync(ran.data(), c->d_ran, ni * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipMemcpyAsync(proxy.data(), c->d_proxy, ni * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    for (int k = 0; k < ni; ++k) {
+        if (!c->inst[k].active || c->plan_h[k].count == 0) continue;
+        const int64_t e = ran[k] > 0 ? (int64_t)ran[k] : epochs;
+        c->inst[k].t += e * (int64_t)c->plan_h[k].count;
+        c->ran_h[k] += e;
+        c->proxy_h[k] = proxy[k];
+        if (ran[k] > 0) c->inst[k].active = false;
+    }
     return ASAGA_OK;
 }
 
@@ -1060,6 +1102,45 @@ int asaga_set_active(asaga_ctx* c, const uint8_t* active) {
     for (size_t k = 0; k < c->inst.size(); ++k)
         if (active[k] > 1) return fail(c, ASAGA_E_ARG, "active entries must be 0 or 1");
     for (size_t k = 0; k < c->inst.size(); ++k) c->inst[k].active = active[k] != 0;
+    return ASAGA_OK;
+}
+
+int asaga_set_stop(asaga_ctx* c, const double* thresholds) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!c->d_insts) return fail(c, ASAGA_E_STATE, "asaga_set_stop needs a batched context");
+    if (!thresholds) {
+        c->stop_on = false;
+        return ASAGA_OK;
+    }
+    const int64_t ni = (int64_t)c->inst.size();
+    for (int64_t k = 0; k < ni; ++k)
+        if (!(thresholds[k] >= 0.0)) return fail(c, ASAGA_E_ARG, "stop thresholds must be >= 0");
+    int rc = ASAGA_OK;
+    if (!c->d_stop_thr) {
+        if ((rc = dalloc(c, &c->d_stop_thr, ni)) || (rc = dalloc(c, &c->d_proxy, ni)) ||
+            (rc = dalloc(c, &c->d_ran, ni)))
+            return rc;
+    }
+    // a call still running may read the thresholds
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    HIPCHK(c, hipMemcpyAsync(c->d_stop_thr, thresholds, ni * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    if (c->proxy_h.size() != (size_t)ni) {
+        c->proxy_h.assign(ni, std::nan(""));
+        c->ran_h.assign(ni, 0);
+    }
+    c->stop_on = true;
+    return ASAGA_OK;
+}
+
+int asaga_stop_report(asaga_ctx* c, double* proxy_out, int64_t* epochs_out) {
+    if (!c) return fail(nullptr, ASAGA_E_ARG, "NULL context");
+    if (!c->d_insts) return fail(c, ASAGA_E_STATE, "asaga_stop_report needs a batched context");
+    const size_t ni = c->inst.size();
+    for (size_t k = 0; k < ni; ++k) {
+        if (proxy_out) proxy_out[k] = k < c->proxy_h.size() ? c->proxy_h[k] : std::nan("");
+        if (epochs_out) epochs_out[k] = k < c->ran_h.size() ? c->ran_h[k] : 0;
+    }
     return ASAGA_OK;
 }
 
@@ -1124,6 +1205,10 @@ int asaga_epochs(asaga_ctx* c, int64_t n_epochs) {
             if (rc) return rc;
         }
         return ASAGA_OK;
+    }
+    if (c->stop_on) {
+        c->proxy_h.assign(c->inst.size(), std::nan(""));
+        c->ran_h.assign(c->inst.size(), 0);
     }
     for (int64_t done = 0; done < n_epochs;) {
         const int64_t e = std::min(n_epochs - done, kMaxGraphEpochs);
@@ -1668,7 +1753,14 @@ int asaga_autotune(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tune
     if (!(target > 0.0 && target < 1.0)) return fail(c, ASAGA_E_ARG, "target must be in (0, 1)");
     if (probe_epochs < 3 || probe_epochs > 1000) return fail(c, ASAGA_E_ARG, "probe_epochs must be in [3, 1000]");
     c->widen_gamma = 0.0;
-    if (c->d_insts) return autotune_batched(c, target, probe_epochs, rep);
+    if (c->d_insts) {
+        // the tuner's probes run whole epochs: no stop test meanwhile
+        const bool stop = c->stop_on;
+        c->stop_on = false;
+        const int rc = autotune_batched(c, target, probe_epochs, rep);
+        c->stop_on = stop;
+        return rc;
+    }
     Inst& I = c->inst[0];
     const UpdateShape base = c->shape;
     const double serial_rule = c->o.step > 0.0 ? c->o.step : I.rule;

@@ -110,6 +110,11 @@ size_t update_lds_bytes(const UpdateShape& S);
 
 // initialisation
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t count, hipStream_t st);
+// stop test of a batch after epoch `epoch` of a call: proxy[k] = ||abar_k +
+// lambda_k x_k||^2 for each instance k < n_inst still running; at or below
+// thr[k] the instance is switched off (insts[k].count = 0, ran[k] = epoch + 1)
+hipError_t launch_batch_proxy(InstArgs* insts, int n_inst, int64_t d, int layout, const double* thr, double* proxy,
+                              int32_t* ran, int32_t epoch, hipStream_t st);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, int64_t stride, hipStream_t st);
 hipError_t launch_fill_f32(float* p, float v, int64_t count, hipStream_t st);
 hipError_t launch_fill_i64(long long* p, long long v, int64_t count, hipStream_t st);

@@ -1088,6 +1088,62 @@ hipError_t launch_sum_x2(XView x, int64_t d, double* part, double* out, hipStrea
     return hipGetLastError();
 }
 
+// In-graph stop test of a batch, after epoch `epoch` of a call (0-based):
+// for every instance still running, r_k = ||abar_k + lambda_k x_k||^2, the
+// gradient of instance k's objective with each row's scalar derivative
+// taken from the memory (alpha_j, from when row j was last sampled) instead
+// of at x: O(d) instead of a pass over the instance's rows.  An instance
+// with r_k <= thr[k] is switched off for the rest of the call (count = 0 in
+// its descriptor, which the call's later launches read) and ran[k] = epoch
+// + 1 records the epochs it applied.  One workgroup per instance; the
+// threads read x and abar by column in the state layout LAY.
+template <int LAY>
+__global__ void __launch_bounds__(1024) k_batch_proxy(InstArgs* insts, int64_t d, const double* thr, double* proxy,
+                                                      int32_t* ran, int32_t epoch) {
+    const int k = blockIdx.x;
+    if (insts[k].count == 0) return;  // off before this epoch (the whole workgroup returns)
+    const double* xd = insts[k].xa;
+    const float* xf = reinterpret_cast<const float*>(xd);
+    const double lam = insts[k].lambda;
+    double s = 0.0, c = 0.0;
+#pragma unroll 4
+    for (int64_t v = threadIdx.x; v < d; v += 1024) {
+        double x, ab;
+        if (LAY == kLayF64) {
+            x = xd[2 * v];
+            ab = xd[2 * v + 1];
+        } else if (LAY == kLayMixed) {
+            x = (double)xf[4 * v];
+            ab = xd[2 * v + 1];
+        } else {
+            x = (double)xf[2 * v];
+            ab = (double)xf[2 * v + 1];
+        }
+        const double g = ab + lam * x;
+        neumaier(s, c, g * g);
+    }
+    const double r = block_sum<1024>(s + c);
+    if (threadIdx.x == 0) {
+        proxy[k] = r;
+        if (r <= thr[k]) {
+            insts[k].count = 0;
+            ran[k] = epoch + 1;
+        }
+    }
+}
+
+hipError_t launch_batch_proxy(InstArgs* insts, int n_inst, int64_t d, int layout, const double* thr, double* proxy,
+                              int32_t* ran, int32_t epoch, hipStream_t st) {
+    if (n_inst <= 0) return hipSuccess;
+    switch (layout) {
+        case kLayF64: k_batch_proxy<kLayF64><<<n_inst, 1024, 0, st>>>(insts, d, thr, proxy, ran, epoch); break;
+        case kLayMixed: k_batch_proxy<kLayMixed><<<n_inst, 1024, 0, st>>>(insts, d, thr, proxy, ran, epoch); break;
+        case kLayF32: k_batch_proxy<kLayF32><<<n_inst, 1024, 0, st>>>(insts, d, thr, proxy, ran, epoch); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 __global__ void k_objective_finish(const double* sums, double m, double lambda, double* f) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *f = sums[0] / m + 0.5 * lambda * sums[1];
 }
