@@ -364,8 +364,10 @@ def batched_throughput(args, dev, stream, precisions=None):
     config-5 batch active: `warmup` launches, then `steps` launches in one
     asaga_epochs call (replayed from its captured hipGraph), at the default
     step law and automatic workgroups (what asaga_autotune chooses on this
-    batch); updates/s from the instances' sample counters and HIP events
-    on the library's stream, and the algorithmic HBM rate."""
+    batch), with the stop test armed at threshold 0 (its O(d) proxy kernel
+    after every launch, as in the solve; no instance stops); updates/s from
+    the instances' sample counters and HIP events on the library's stream,
+    and the algorithmic HBM rate."""
     import numpy as np
     import torch
 
@@ -383,6 +385,7 @@ def batched_throughput(args, dev, stream, precisions=None):
     for prec in precisions or (A.ASAGA_PREC_F32, A.ASAGA_PREC_F64):
         g = A.Solver(p.n, p.d, *arrs, p.lam, loss=p.loss, val_dtype=A.ASAGA_VAL_BF16, mode=A.ASAGA_MODE_ASYNC,
                      precision=prec, stream=stream, batch=(B.row_fold, B.inst_fold, B.inst_lambda))
+        g.set_stop(np.zeros(B.n_inst))
         g.epochs(args.warmup)
         torch.cuda.synchronize()
         t0 = sum(g.instance(k).t for k in range(B.n_inst))
