@@ -569,9 +569,9 @@ def run_until(g, fstar, stream, target=1e-9, max_epochs=800, every=5):
 
 def config3_leg(dev, stream):
     """The Covtype-shaped least squares (581,000 x 54, the same ten dense
-    columns in every row): FP64 async, autotuned; then FP32 state (100
-    epochs, where FP32 x stalls near 1e-7), widened to FP64 and polished to
-    1e-9."""
+    columns in every row): FP64 async, autotuned; then FP32 state (up to 100
+    epochs, checked every 10), widened to FP64 and polished to 1e-9 if it
+    stalled above it."""
     import numpy as np
     import torch
 
@@ -602,13 +602,17 @@ def config3_leg(dev, stream):
                  stream=stream)
     rep = g.autotune(target=1e-9, probe_epochs=9)
     ep32, s32, rel32 = run_until(g, fstar, stream, max_epochs=100, every=10)
-    g.widen()
-    ep64, s64, rel64 = run_until(g, fstar, stream, every=10)
+    ep64, s64, rel64 = 0, 0.0, rel32
+    if rel32 > 1e-9:
+        # FP32 x stalled above the target: the FP64 polish finishes
+        g.widen()
+        ep64, s64, rel64 = run_until(g, fstar, stream, every=10)
     out["fp32_then_fp64"] = {"fp32_epochs": ep32, "fp32_seconds": s32, "rel_subopt_fp32": rel32,
                              "fp64_epochs": ep64, "fp64_seconds": s64, "final_rel_subopt": rel64,
                              "reached": rel64 <= 1e-9, "seconds_to_1e-9": s32 + s64,
                              "fp32_updates_per_s": ep32 * p.n / s32 if s32 > 0 else None,
-                             "waves": rep.waves, "gamma": rep.gamma, "fp64_polish_gamma": rep.widen_gamma}
+                             "waves": rep.waves, "gamma": rep.gamma,
+                             "fp64_polish_gamma": rep.widen_gamma if ep64 else None}
     g.close()
     log(f"config3 FP32 then FP64: {out['fp32_then_fp64']}")
     return out
