@@ -56,15 +56,25 @@ def load_golden():
 
 
 def host_cpu_model():
-    """The host CPU's model name from /proc/cpuinfo, or None."""
+    """The host CPU as /proc/cpuinfo (what lscpu reads) names it: model name,
+    then family, model and stepping numbers (a virtualised host may shorten
+    the name; the numbers still identify the generation), or None."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as fh:
             for line in fh:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break                       # the first processor's block only
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    fields.setdefault(k.strip(), v.strip())
     except OSError:
-        pass
-    return None
+        return None
+    name = fields.get("model name")
+    if name is None:
+        return None
+    nums = [f"{k} {fields[k]}" for k in ("cpu family", "model", "stepping") if k in fields]
+    return f"{name} ({', '.join(nums)})" if nums else name
 
 
 def kernel_source_digest() -> str:
