@@ -604,7 +604,8 @@ def config3_leg(dev, stream):
     ep, secs, rel = run_until(g, fstar, stream)
     out["fp64"] = {"epochs": ep, "seconds_to_1e-9": secs, "final_rel_subopt": rel, "reached": rel <= 1e-9,
                    "updates_per_s": ep * p.n / secs, "hbm_gbps_algorithmic": bpu * ep * p.n / secs / 1e9,
-                   "waves": rep.waves, "gamma_over_serial_rule": rep.gamma * 3.0 * g.info().L,
+                   "waves": rep.waves, "threads_per_block": rep.threads_per_block,
+                   "gamma_over_serial_rule": rep.gamma * 3.0 * g.info().L,
                    "autotune_wall_s": tune_s}
     g.close()
     log(f"config3 FP64: {out['fp64']}")
@@ -621,7 +622,7 @@ def config3_leg(dev, stream):
                              "fp64_epochs": ep64, "fp64_seconds": s64, "final_rel_subopt": rel64,
                              "reached": rel64 <= 1e-9, "seconds_to_1e-9": s32 + s64,
                              "fp32_updates_per_s": ep32 * p.n / s32 if s32 > 0 else None,
-                             "waves": rep.waves, "gamma": rep.gamma,
+                             "waves": rep.waves, "threads_per_block": rep.threads_per_block, "gamma": rep.gamma,
                              "fp64_polish_gamma": rep.widen_gamma if ep64 else None}
     g.close()
     log(f"config3 FP32 then FP64: {out['fp32_then_fp64']}")
@@ -942,7 +943,8 @@ def main():
         g = make_solver(0.0)   # the ladder starts from the serial rule
         rep = g.autotune(target=1e-9, probe_epochs=9)
         g.close()
-        tune = {"candidates": rep.candidates, "waves": rep.waves, "hot_columns": rep.hot_columns,
+        tune = {"candidates": rep.candidates, "waves": rep.waves, "threads_per_block": rep.threads_per_block,
+                "hot_columns": rep.hot_columns,
                 "hot_tier_columns": rep.hot_tier_columns, "gamma": rep.gamma, "ms_per_epoch": rep.ms_per_epoch,
                 "est_epochs": rep.est_epochs, "est_seconds": rep.est_seconds, "tuning_wall_s": time.time() - t}
         log(f"autotune: {tune}")

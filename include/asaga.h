@@ -282,6 +282,8 @@ typedef struct asaga_tune_report {
                                  FP32 x, when gamma is the largest stable step
                                  probed at its wavefront count, the next smaller
                                  one (gamma * 2^(-1/3)); batches: gamma         */
+    int32_t threads_per_block; /* chosen workgroup size                             */
+    int32_t reserved;
 } asaga_tune_report;
 
 /* Create a context for the problem of Section 1 (Eq. finiteSum with the
@@ -472,8 +474,8 @@ int asaga_widen(asaga_ctx* ctx);
 
 /* Choose the number of wavefronts in flight and the step that reach
  * relative suboptimality `target` soonest on this problem (async contexts;
- * the other shape parameters stay as the context has them, except as said
- * for batches below).
+ * the other shape parameters stay as the context has them, except the
+ * workgroup size as said below and for batches).
  * Fewer samples in flight tolerate a larger step (Theorem 2) but take longer
  * per epoch, so wavefront counts are tried from one workgroup per compute
  * unit (at most n/64 samples in flight) down to 1/8 wavefront per compute
@@ -503,10 +505,16 @@ int asaga_widen(asaga_ctx* ctx);
  * noise floor does not show) is within `target` of the last one (with FP32 x: a tenth of `target`, so
  * that a run stalling at its FP32 floor just above it does not count), and
  * drops out once its kernel time reaches the best finished one's, once it
- * makes no new minimum for three checks, or after 40 * probe_epochs epochs.  The one finished in the least kernel
+ * makes no new minimum for three checks, or after 40 * probe_epochs epochs.
+ * The one finished in the least kernel
  * time is kept, and the report's est_epochs and est_seconds are its
  * measured epochs and kernel time to finish; if none finishes, the one
  * that got lowest is kept, with the epochs it ran and their kernel time.
+ * Unless opts.threads_per_block is set, a finished winner then runs once
+ * more in workgroups half as large (at least 256 threads: the same
+ * wavefronts over twice the compute units, a shorter latency per sample but
+ * fewer samples per hot set), timed for one epoch first, and replaces it if
+ * it finishes in less kernel time.
  * In the probes, with FP32 x (ASAGA_PREC_MIXED, ASAGA_PREC_F32), a gradient
  * norm at the floor FP32 rounding leaves (8 * 2^-24 * L * ||x||) no longer
  * has to fall, so that stalling there is not taken for instability; it

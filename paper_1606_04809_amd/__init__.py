@@ -89,7 +89,8 @@ class asaga_tune_report(ctypes.Structure):
                 ("hot_tier_columns", ctypes.c_int32), ("gamma", ctypes.c_double), ("ms_per_epoch", ctypes.c_double),
                 ("est_epochs", ctypes.c_double), ("est_seconds", ctypes.c_double),
                 ("step_groups", ctypes.c_double), ("step_cap", ctypes.c_double),
-                ("widen_gamma", ctypes.c_double)]
+                ("widen_gamma", ctypes.c_double), ("threads_per_block", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class asaga_overlap_report(ctypes.Structure):

@@ -524,6 +524,7 @@ def test_autotune_picks_a_stable_shape_and_converges():
         assert rep.candidates >= 4 and rep.gamma > 0 and rep.est_epochs >= 9
         info = g.info()
         assert info.t == 0 and info.gamma == rep.gamma and info.waves == rep.waves
+        assert info.threads_per_block == rep.threads_per_block
         assert np.all(g.get_x() == 0.0)
         for e in range(40):
             g.epochs(5)
