@@ -535,7 +535,7 @@ int asaga_widen(asaga_ctx* ctx);
  * passes.  The hot-set sizes are ranked by those estimated epochs times one
  * epoch of every active instance under their law.  cap is then the largest of 1, 1/2,
  * 1/4, 1/8 with which no active instance is unstable with all of them
- * running, where among many instances unstable means a squared gradient
+ * running (1 with one active instance: the calibration has run it so), where among many instances unstable means a squared gradient
  * norm that more than doubles between checkpoints or does not decrease from
  * the first to the last (single checkpoints without decrease are noise of
  * the asynchronous updates).  `waves` in the report is per instance with all

@@ -1692,9 +1692,19 @@ int autotune_batched(asaga_ctx* c, double target, int32_t probe_epochs, asaga_tu
         }
         if (!ok && !rc) best.est_s = INFINITY;
     }
-    // 2. every instance running: the largest stable cap
+    // 2. every instance running: the largest stable cap.  With one active
+    // instance cap 1 is the run the calibration has just verified (that
+    // instance alone on step_groups lane groups at the full step, three
+    // times longer than a probe).  A short probe repeating it at a law on
+    // the edge of stability can fail by chance, and a smaller cap gives the
+    // lone instance more lane groups at a proportionally smaller step: on
+    // the URL-shaped instance cap 1/8 (416 wavefronts) hovered near 3e-4
+    // where cap 1 (64 wavefronts) reached 1e-9 in 30 epochs.
     double cap = 0.0;
-    if (!rc && std::isfinite(best.est_s)) {
+    int n_was = 0;  // instances the caller has switched on
+    for (size_t k = 0; k < ni; ++k) n_was += was_active[k] ? 1 : 0;
+    if (!rc && std::isfinite(best.est_s) && n_was == 1) cap = 1.0;
+    if (!rc && std::isfinite(best.est_s) && n_was > 1) {
         set_active(false);
         c->shape = best.S;
         c->step_groups = best.groups;
