@@ -180,10 +180,10 @@ def solve_with_stop_test(g, check, stream, target=1e-9, max_launches=600, eager=
     instance; otherwise it (re)calibrates the threshold to the proxy at
     which rel/proxy as measured there would put the instance at eager *
     target, and an instance the test stopped early runs on.  Returns the
-    kernel seconds between HIP events, the counts of launches, checks and
-    early stops, and each instance's last checked value and samples."""
+    kernel seconds between HIP events on `stream` (host seconds around each
+    call when `stream` is None), the counts of launches, checks and early
+    stops, and each instance's last checked value and samples."""
     import numpy as np
-    import torch
 
     ni = g.n_inst
     active = np.ones(ni, dtype=np.uint8)
@@ -193,15 +193,22 @@ def solve_with_stop_test(g, check, stream, target=1e-9, max_launches=600, eager=
     applied = np.zeros(ni, dtype=np.int64)
     g.set_active(active)
     g.set_stop(thr)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if stream is not None:
+        import torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     kernel_s, launches, checks, early, pairs = 0.0, 0, 0, 0, 0
     while active.any() and launches < max_launches:
         pairs += int(active.sum())
-        e0.record(stream)
-        g.epochs(1)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        kernel_s += e0.elapsed_time(e1) / 1e3
+        if stream is not None:
+            e0.record(stream)
+            g.epochs(1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            kernel_s += e0.elapsed_time(e1) / 1e3
+        else:
+            t0 = time.perf_counter()
+            g.epochs(1)
+            kernel_s += time.perf_counter() - t0
         launches += 1
         proxy, _ = g.stop_report()
         for k in np.nonzero(active)[0]:
