@@ -367,7 +367,9 @@ int asaga_set_active(asaga_ctx* ctx, const uint8_t* active);
 int asaga_set_stop(asaga_ctx* ctx, const double* thresholds);
 
 /* Batched contexts: what the stop test saw in the last asaga_epochs call
- * with it armed.  proxy_out (double[n_inst], or NULL): r_k after the last
+ * with it armed (the proxy of asaga_set_stop: the Section 4.1 objective's
+ * gradient with the derivatives held in the memory of Section 2).
+ * proxy_out (double[n_inst], or NULL): r_k after the last
  * epoch instance k ran in that call (NaN if it ran none); epochs_out
  * (int64_t[n_inst], or NULL): the epochs (launches) it ran, fewer than the
  * call's where the test switched it off.  Before any such call: NaN and 0. */
