@@ -125,6 +125,12 @@ def test_null_context_calls_fail_cleanly():
     assert lib.asaga_epochs(None, 1) == A.ASAGA_E_ARG
     lib.asaga_set_active.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     assert lib.asaga_set_active(None, None) == A.ASAGA_E_ARG
+    lib.asaga_set_stop.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.asaga_set_stop(None, None) == A.ASAGA_E_ARG
+    lib.asaga_stop_report.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.asaga_stop_report(None, None, None) == A.ASAGA_E_ARG
+    lib.asaga_widen.argtypes = [ctypes.c_void_p]
+    assert lib.asaga_widen(None) == A.ASAGA_E_ARG
     lib.asaga_free.argtypes = [ctypes.c_void_p]
     lib.asaga_free(None)
 
